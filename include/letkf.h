@@ -1,0 +1,208 @@
+/*
+ * letkf.h -- C-ABI of an MI355X (gfx950) library for the LETKF local analysis
+ * applied at every grid point of a D2Q9 lattice-Boltzmann ensemble.
+ *
+ * What is computed (arXiv 2308.03310, Sec. II-B and Algorithm 1): for every
+ * grid point, the R-localized local problem
+ *
+ *     Q    = ((k-1)/rho) I + dY^T R_loc^-1 dY          eq. (letkf_q), inflated
+ *     Pa   = Q^-1,  wbar = Pa dY^T R_loc^-1 (yo - ybar) eq. (letkf_wa)
+ *     dW   = sqrt(k-1) Pa^(1/2)                         eq. (letkf_dwa)
+ *     x^a_m = xbar + dX (wbar + dw_m)                    eq. (letkf_xa)
+ *
+ * where dY are the forecast-observation perturbations H(x_m) - ybar (eqs.
+ * enkf_ybar, enkf_deltay; H takes density or velocity moments, Sec. II-A),
+ * R_loc^-1 = G o R^-1 with a diagonal localization G (Sec. II-B), and the
+ * nine distribution functions of a point share one transform (Sec. II-B).
+ * Pa and Pa^(1/2) come from a symmetric eigendecomposition of Q (Sec. III).
+ *
+ * Layout conventions
+ *   - ensembles are member-major FP64:  f[k][9][ny][nx], flat index
+ *     ((m*9 + i)*ny + y)*nx + x, on the device;
+ *   - D2Q9 direction order i = 0..8:
+ *       c = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1);
+ *   - the lattice is periodic in x and y; distances are minimum-image
+ *     Euclidean lattice distances.
+ *
+ * Ownership: the caller owns every array passed in (device memory) and the
+ * HIP stream; a plan owns its device workspace, which is allocated in
+ * letkf_plan() only (analyze/cycle never allocate).  A plan is bound to the
+ * device that was current when it was made and is used by one stream at a
+ * time.
+ *
+ * Errors: every call returns an int status (no exceptions cross the ABI).
+ * Argument errors found on the host return before anything is enqueued.
+ * Errors found on the device (invalid observation record, non-finite result,
+ * eigensolver not converged) are recorded in the plan and reported by
+ * letkf_status(); when an invalid observation is found the analysis output
+ * is left unwritten.
+ */
+#ifndef LETKF_H
+#define LETKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LETKF_OK          0
+#define LETKF_EINVAL      1  /* invalid argument (host check) or invalid observation (device check) */
+#define LETKF_ENOMEM      2  /* workspace exceeds the HBM budget or device allocation failed */
+#define LETKF_EDEVICE     3  /* no usable gfx950 device, or a HIP runtime error */
+#define LETKF_EBUSY       4  /* plan in use by another call */
+#define LETKF_ENONFINITE  5  /* a non-finite analysis value was produced */
+#define LETKF_ENOTCONV    6  /* eigensolver hit its sweep limit before converging */
+
+/* ---- enums ---- */
+/* Localization function G (Sec. II-B, R-localization). */
+#define LETKF_LOC_GAUSS   0  /* exp(-r^2/(2L^2)) for r <= 2L (inclusive), else 0 */
+#define LETKF_LOC_GC      1  /* Gaspari-Cohn 5th-order, half-width L, zero for r >= 2L */
+#define LETKF_LOC_NONE    2  /* G = 1: every observation is local (global ETKF) */
+
+/* Arithmetic of the Gram and update contractions.  Forecast observations,
+ * the eigensolve and the eigenvalue scaling are FP64 in every form. */
+#define LETKF_PREC_FP64   0
+#define LETKF_PREC_FP32   1
+#define LETKF_PREC_BF16   2
+
+/* Observed variable at a lattice point (moments, Sec. II-A). */
+#define LETKF_OBS_RHO     0  /* density  sum_i f_i */
+#define LETKF_OBS_U       1  /* x-velocity (sum_i c_x,i f_i) / rho */
+#define LETKF_OBS_V       2  /* y-velocity (sum_i c_y,i f_i) / rho */
+
+#define LETKF_MAX_K       64 /* largest ensemble size (one wavefront row per member) */
+
+/* One analysis problem's shape and parameters. */
+typedef struct letkf_problem {
+  int32_t nx, ny;       /* periodic lattice size, >= 1 each */
+  int32_t k;            /* ensemble size M, 2 <= k <= LETKF_MAX_K */
+  int32_t n_obs_max;    /* largest observation count a call may pass, >= 0 */
+  double  loc_len;      /* localization length L (lattice units), finite, > 0 */
+  double  infl;         /* multiplicative inflation rho, finite, > 0 */
+  int32_t loc;          /* LETKF_LOC_* */
+  int32_t precision;    /* LETKF_PREC_* */
+} letkf_problem;
+
+/* Plan flags. */
+#define LETKF_FLAG_PHASE_TIMING 1  /* record HIP events around every kernel phase */
+
+/* Plan options (pass NULL for the defaults: no budget, no flags). */
+typedef struct letkf_options {
+  uint64_t hbm_budget_bytes;  /* workspace limit; 0 = no limit */
+  int32_t  flags;             /* LETKF_FLAG_* */
+  int32_t  reserved;
+} letkf_options;
+
+typedef struct letkf_plan_s* letkf_plan_t;
+
+/*
+ * letkf_plan -- validate the problems and allocate all device workspace.
+ *   probs[n_probs]: problem descriptors (host memory, copied).
+ *   opt:            may be NULL.
+ *   out:            receives the plan handle (set to NULL on error).
+ * Returns LETKF_EINVAL (any descriptor out of range, n_probs < 1, out NULL),
+ * LETKF_ENOMEM (workspace above hbm_budget_bytes or hipMalloc failure) or
+ * LETKF_EDEVICE (no gfx950 device).  Host checks run before any device call.
+ */
+int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options* opt,
+               letkf_plan_t* out);
+
+/* One analysis call: background in, analysis out (Algorithm 1 REQUIRE/ENSURE). */
+typedef struct letkf_io {
+  int32_t problem;          /* index into the plan's problems */
+  int32_t n_obs;            /* 0 <= n_obs <= n_obs_max */
+  const double*  xb;        /* device, [k][9][ny][nx] forecast ensemble */
+  double*        xa;        /* device, [k][9][ny][nx] analysis; may equal xb */
+  const int32_t* obs_ix;    /* device, [n_obs] lattice x in [0, nx) */
+  const int32_t* obs_iy;    /* device, [n_obs] lattice y in [0, ny) */
+  const int32_t* obs_kind;  /* device, [n_obs] LETKF_OBS_* */
+  const double*  obs_val;   /* device, [n_obs] observed values y^o */
+  const double*  obs_var;   /* device, [n_obs] error variances sigma^2 (R diagonal);
+                               > 0, +inf means "ignore this observation" */
+} letkf_io;
+
+/*
+ * letkf_analyze -- enqueue n_io analyses on hip_stream (a hipStream_t, or
+ * NULL for the null stream).  Asynchronous and stream-ordered; returns after
+ * host checks (LETKF_EINVAL: bad problem index, n_obs out of range, NULL
+ * pointer with n_obs > 0 or NULL xb/xa).  Device-side observation checks
+ * (index range, kind, variance > 0 or +inf, finite value) set the plan status
+ * to LETKF_EINVAL and skip the analysis.  In-place (xa == xb) is legal: the
+ * background is fully consumed before any analysis value is written.
+ */
+int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream);
+
+/* One data-assimilation cycle (Sec. II-B, DA cycle steps 2-3): n_steps
+ * lattice-BGK steps with relaxation time tau and a Kolmogorov body force
+ * F_x(y) = force_amp * sin(2 pi force_kx y / ny), then one analysis.  The
+ * ensemble is advanced and analysed in place: io.xa must equal io.xb. */
+typedef struct letkf_cycle_io {
+  letkf_io io;
+  int32_t  n_steps;    /* >= 0 */
+  int32_t  force_kx;   /* forcing wavenumber */
+  double   tau;        /* BGK relaxation time, > 0.5 */
+  double   force_amp;  /* body-force amplitude */
+} letkf_cycle_io;
+
+int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream);
+
+/*
+ * letkf_status -- device-detected status of the plan's calls since the last
+ * letkf_status.  sync != 0 waits for the plan's last stream first (otherwise
+ * the value reflects only completed work).  Returns LETKF_OK or the first
+ * error code; the status is cleared after reading.
+ */
+int letkf_status(letkf_plan_t plan, int32_t sync);
+
+/* Release the plan's workspace.  NULL is accepted. */
+int letkf_plan_destroy(letkf_plan_t plan);
+
+/* Static string for a status code. */
+const char* letkf_strerror(int code);
+
+/* Device bytes held by the plan's workspace. */
+uint64_t letkf_plan_workspace_bytes(letkf_plan_t plan);
+
+/* Phases of one analysis, in launch order. */
+#define LETKF_PHASE_BIN        0  /* observation checks + cell binning */
+#define LETKF_PHASE_TRANSPOSE  1  /* member-major -> point-major ensemble */
+#define LETKF_PHASE_OBSOP      2  /* forecast observations, mean, perturbations */
+#define LETKF_PHASE_GRAM       3  /* localized Gram matrix and right-hand side */
+#define LETKF_PHASE_EVD        4  /* eigensolve, transform, update */
+#define LETKF_PHASE_UNTRANS    5  /* point-major -> member-major analysis */
+#define LETKF_N_PHASES         6
+
+/*
+ * letkf_phase_times -- for a plan made with LETKF_FLAG_PHASE_TIMING: waits for
+ * the plan's last stream, then writes the summed GPU time (ms, from HIP
+ * events recorded on the analysis stream) of each phase over the analyze
+ * calls since the previous letkf_phase_times (at most the last 256 calls;
+ * with n_io > 1 the first analysis of each call is timed) to ms[0..n-1], the
+ * number of kernel launches of each phase per timed call to launches[0..n-1]
+ * (may be NULL) and returns the number of calls summed (>= 0), or -LETKF_*
+ * on error.  Resets the accumulation.
+ */
+int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t n);
+
+/*
+ * letkf_eigh_batched -- batched symmetric eigendecomposition (the role of the
+ * batched EVD of Sec. III), FP64, one k x k matrix per problem.
+ *   a:   device, [batch][k][k] symmetric matrices (row-major; the upper
+ *        triangle is read), 1 <= k <= LETKF_MAX_K;
+ *   lam: device, [batch][k] eigenvalues (ascending order is NOT guaranteed);
+ *   vec: device, [batch][k][k], column j is the eigenvector of lam[j].
+ *   status: device int32 (may be NULL); bit (1 << LETKF_ENOTCONV) is OR-ed
+ *        in if a matrix did not converge.
+ * Asynchronous on hip_stream.  Returns LETKF_EINVAL for bad sizes or NULL
+ * pointers.
+ */
+int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, double* vec,
+                       int32_t* status, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LETKF_H */

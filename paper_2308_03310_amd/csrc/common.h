@@ -1,0 +1,85 @@
+// Device-side helpers shared by the gfx950 kernels of the LETKF library.
+// Wavefront size is 64 throughout; every kernel is written for CDNA4.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace letkf {
+
+constexpr int kWave = 64;
+
+// D2Q9 directions in the library's order (see include/letkf.h):
+// (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+__host__ __device__ constexpr int cx_of(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+
+// Status bits kept in the plan's device status word (bit n <-> error code n).
+constexpr int kStatEinval = 1 << 1;
+constexpr int kStatNonfinite = 1 << 5;
+constexpr int kStatNotconv = 1 << 6;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Make LDS writes of this wavefront visible to its other lanes (and keep the
+// compiler from moving LDS accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane exchange lane <-> lane ^ M for a 32-bit value.  Masks below 32 use the
+// swizzle network (bitmask mode, within 32-lane halves); larger masks use
+// ds_bpermute.
+template <int M>
+__device__ __forceinline__ int xor_lane_i32(int x) {
+  static_assert(M > 0 && M < 64, "xor mask");
+  if constexpr (M < 32) {
+    return __builtin_amdgcn_ds_swizzle(x, (M << 10) | 0x1F);
+  } else {
+    return __builtin_amdgcn_ds_bpermute((lane_id() ^ M) << 2, x);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+  const int lo = xor_lane_i32<M>(__double2loint(x));
+  const int hi = xor_lane_i32<M>(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// Butterfly sum over aligned groups of G lanes (G a power of two <= 64).
+// Every lane of a group receives the bitwise-identical total (IEEE addition
+// is commutative and the tree is symmetric).
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (G >= 64) x += xor_lane<32>(x);
+  if constexpr (G >= 32) x += xor_lane<16>(x);
+  if constexpr (G >= 16) x += xor_lane<8>(x);
+  if constexpr (G >= 8) x += xor_lane<4>(x);
+  if constexpr (G >= 4) x += xor_lane<2>(x);
+  if constexpr (G >= 2) x += xor_lane<1>(x);
+  return x;
+}
+
+// Block index remap so that consecutive logical blocks land on the same XCD
+// (blocks are dispatched round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int nb8 = nblocks >> 3, rem = nblocks & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd < rem ? xcd * (nb8 + 1) + idx : rem * (nb8 + 1) + (xcd - rem) * nb8 + idx;
+}
+
+__host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace letkf

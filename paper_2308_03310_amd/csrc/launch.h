@@ -1,0 +1,99 @@
+// Host-side launchers of the gfx950 kernels and their argument blocks.
+// Internal to the library; the public surface is include/letkf.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace letkf {
+
+// Observation binning (uniform cells of cb x cb lattice points) and the
+// forecast-observation operator.
+struct ObsArgs {
+  int nx, ny, k, kq, npts;
+  int n_obs;
+  int cb, ncx, ncy, ncells;
+  const int32_t* ix;
+  const int32_t* iy;
+  const int32_t* kind;
+  const double* val;
+  const double* var;
+  int* obs_cell;    // [n_obs]   cell of each observation, -1 if invalid
+  int* cell_count;  // [ncells]
+  int* cell_start;  // [ncells + 1] exclusive scan; cell_start[ncells] = valid count
+  int* cell_fill;   // [ncells]
+  int* perm;        // [n_obs]   sorted slot -> observation index
+  int* ox;          // [n_obs]   sorted slot -> lattice x
+  int* oy;
+  double* Yb;       // [n_obs][kq] forecast-observation perturbations (zero padded to KP)
+  double* d;        // [n_obs] yo - ybar
+  double* rinv;     // [n_obs] 1/sigma^2 (0 for an ignored observation)
+  const double* xt; // point-major ensemble [npts][9][k]
+  int* abort_flag;
+  int* status;
+};
+
+// Localized Gram matrix C = dY^T R_loc^-1 dY and b = dY^T R_loc^-1 d per point.
+struct GramArgs {
+  int nx, ny, k;
+  int pt0, npt;       // this launch covers points [pt0, pt0 + npt)
+  int cb, ncx, ncy;
+  int R;              // window radius in lattice units; < 0 means every cell
+  int loc;            // LETKF_LOC_*
+  double cut2;        // r^2 cutoff (inclusive for the Gaussian)
+  double inv2L2;      // 1 / (2 L^2)
+  double invL;        // 1 / L   (Gaspari-Cohn)
+  const int* cell_start;
+  const int* ox;
+  const int* oy;
+  const double* Yb;
+  const double* d;
+  const double* rinv;
+  double* C;          // [npt][NB][256] upper 16x16 blocks of C
+  double* b;          // [npt][KP]
+  const int* abort_flag;
+};
+
+// Eigensolve of Q = alpha I + C, transform and in-place update of the
+// point-major ensemble (mode 0), or a standalone batched eigensolve (mode 1).
+struct EvdArgs {
+  int mode;
+  int k, npts;
+  int pt0, npt;       // mode 0: points [pt0, pt0 + npt); mode 1: npt matrices
+  double alpha;       // (k - 1) / rho
+  double sqrt_km1;    // sqrt(k - 1)
+  double tol2;        // squared relative off-diagonal tolerance
+  int max_sweeps;
+  const double* C;    // [npt][NB][256] upper 16x16 blocks of C (KP-padded)
+  const double* b;    // [npt][KP]
+  double* xt;         // point-major ensemble [npts][9][k], updated in place
+  const double* A;    // mode 1: [npt][k][k]
+  double* lam;        // mode 1: [npt][k]
+  double* vec;        // mode 1: [npt][k][k]
+  const int* abort_flag;
+  int* status;
+};
+
+// --- launchers (return hipError_t of the launch) ---
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
+hipError_t launch_bin(const ObsArgs& a, hipStream_t s);
+hipError_t launch_transpose_in(const double* xb, double* xt, int k, int npts, const int* abort_flag,
+                               hipStream_t s);
+hipError_t launch_transpose_out(const double* xt, double* xa, int k, int npts,
+                                const int* abort_flag, hipStream_t s);
+hipError_t launch_obs_operator(const ObsArgs& a, hipStream_t s);
+hipError_t launch_gram_f64(const GramArgs& a, int kp, hipStream_t s);
+template <int KP>
+hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s);
+
+inline int pow2_at_least16(int k) {
+  int p = 16;
+  while (p < k) p <<= 1;
+  return p;
+}
+inline int n_upper_blocks(int kp) {
+  const int q = kp / 16;
+  return q * (q + 1) / 2;
+}
+
+}  // namespace letkf

@@ -1,0 +1,212 @@
+"""Python binding of libletkf.so (include/letkf.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Tensors are
+torch tensors on the plan's device (float64 / int32, contiguous); streams
+default to torch's current stream.  All arithmetic runs in the library's
+gfx950 kernels: if the library is missing, loading raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Iterable, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libletkf.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "letkf.h")
+
+LETKF_OK, LETKF_EINVAL, LETKF_ENOMEM, LETKF_EDEVICE = 0, 1, 2, 3
+LETKF_EBUSY, LETKF_ENONFINITE, LETKF_ENOTCONV = 4, 5, 6
+LETKF_LOC_GAUSS, LETKF_LOC_GC, LETKF_LOC_NONE = 0, 1, 2
+LETKF_PREC_FP64, LETKF_PREC_FP32, LETKF_PREC_BF16 = 0, 1, 2
+LETKF_OBS_RHO, LETKF_OBS_U, LETKF_OBS_V = 0, 1, 2
+LETKF_MAX_K = 64
+LETKF_FLAG_PHASE_TIMING = 1
+PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose")
+
+
+class letkf_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("n_obs_max", ctypes.c_int32), ("loc_len", ctypes.c_double),
+                ("infl", ctypes.c_double), ("loc", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class letkf_options(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class letkf_io(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int32), ("n_obs", ctypes.c_int32),
+                ("xb", ctypes.c_void_p), ("xa", ctypes.c_void_p),
+                ("obs_ix", ctypes.c_void_p), ("obs_iy", ctypes.c_void_p),
+                ("obs_kind", ctypes.c_void_p), ("obs_val", ctypes.c_void_p),
+                ("obs_var", ctypes.c_void_p)]
+
+
+class letkf_cycle_io(ctypes.Structure):
+    _fields_ = [("io", letkf_io), ("n_steps", ctypes.c_int32), ("force_kx", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("force_amp", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libletkf.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is missing: build it with paper_2308_03310_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, u64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p
+    lib.letkf_plan.argtypes = [ctypes.POINTER(letkf_problem), i32, ctypes.POINTER(letkf_options),
+                               ctypes.POINTER(vp)]
+    lib.letkf_plan.restype = ctypes.c_int
+    lib.letkf_analyze.argtypes = [vp, ctypes.POINTER(letkf_io), i32, vp]
+    lib.letkf_analyze.restype = ctypes.c_int
+    lib.letkf_cycle.argtypes = [vp, ctypes.POINTER(letkf_cycle_io), i32, vp]
+    lib.letkf_cycle.restype = ctypes.c_int
+    lib.letkf_status.argtypes = [vp, i32]
+    lib.letkf_status.restype = ctypes.c_int
+    lib.letkf_plan_destroy.argtypes = [vp]
+    lib.letkf_plan_destroy.restype = ctypes.c_int
+    lib.letkf_strerror.argtypes = [ctypes.c_int]
+    lib.letkf_strerror.restype = ctypes.c_char_p
+    lib.letkf_plan_workspace_bytes.argtypes = [vp]
+    lib.letkf_plan_workspace_bytes.restype = u64
+    lib.letkf_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int32), i32]
+    lib.letkf_phase_times.restype = ctypes.c_int
+    lib.letkf_eigh_batched.argtypes = [dp, i32, i32, dp, dp, dp, vp]
+    lib.letkf_eigh_batched.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions include/letkf.h declares."""
+    txt = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*|uint64_t)\s+(letkf_\w+)\s*\(", txt, re.M)))
+
+
+class LetkfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {letkf_strerror(code)} ({code})")
+
+
+def _check(code: int, where: str) -> int:
+    if code != LETKF_OK:
+        raise LetkfError(code, where)
+    return code
+
+
+def _ptr(t, dtype=None) -> int:
+    if t is None:
+        return 0
+    import torch
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def letkf_strerror(code: int) -> str:
+    return load_library().letkf_strerror(int(code)).decode()
+
+
+def make_problem(nx, ny, k, n_obs_max, loc_len, infl, loc=LETKF_LOC_GAUSS,
+                 precision=LETKF_PREC_FP64) -> letkf_problem:
+    return letkf_problem(int(nx), int(ny), int(k), int(n_obs_max), float(loc_len), float(infl),
+                         int(loc), int(precision))
+
+
+def letkf_plan(problems: Sequence[letkf_problem], hbm_budget_bytes: int = 0, flags: int = 0,
+               raise_on_error: bool = True):
+    """Returns the plan handle (int), or (code, None) when raise_on_error is False."""
+    lib = load_library()
+    arr = (letkf_problem * len(problems))(*problems) if len(problems) else None
+    opt = letkf_options(int(hbm_budget_bytes), int(flags), 0)
+    h = ctypes.c_void_p()
+    rc = lib.letkf_plan(arr, len(problems), ctypes.byref(opt), ctypes.byref(h))
+    if not raise_on_error:
+        return rc, h.value
+    _check(rc, "letkf_plan")
+    return h.value
+
+
+def make_io(problem: int, xb, xa, obs=None) -> letkf_io:
+    """obs: dict or tuple of device tensors (ix, iy, kind int32; val, var float64)."""
+    import torch
+    if obs is None:
+        n, p = 0, (0, 0, 0, 0, 0)
+    else:
+        if isinstance(obs, dict):
+            obs = (obs["ix"], obs["iy"], obs["kind"], obs["val"], obs["var"])
+        ix, iy, kd, val, var = obs
+        n = int(ix.numel())
+        p = (_ptr(ix, torch.int32), _ptr(iy, torch.int32), _ptr(kd, torch.int32),
+             _ptr(val, torch.float64), _ptr(var, torch.float64))
+    return letkf_io(int(problem), n, _ptr(xb, torch.float64), _ptr(xa, torch.float64), *p)
+
+
+def letkf_analyze(plan: int, ios: Iterable[letkf_io], stream=None) -> int:
+    ios = list(ios)
+    arr = (letkf_io * len(ios))(*ios)
+    return _check(load_library().letkf_analyze(plan, arr, len(ios), _stream(stream)),
+                  "letkf_analyze")
+
+
+def letkf_cycle(plan: int, ios: Iterable[letkf_cycle_io], stream=None) -> int:
+    ios = list(ios)
+    arr = (letkf_cycle_io * len(ios))(*ios)
+    return _check(load_library().letkf_cycle(plan, arr, len(ios), _stream(stream)), "letkf_cycle")
+
+
+def letkf_status(plan: int, sync: bool = True) -> int:
+    return load_library().letkf_status(plan, 1 if sync else 0)
+
+
+def letkf_plan_destroy(plan: Optional[int]) -> int:
+    return load_library().letkf_plan_destroy(plan)
+
+
+def letkf_plan_workspace_bytes(plan: int) -> int:
+    return int(load_library().letkf_plan_workspace_bytes(plan))
+
+
+def letkf_phase_times(plan: int):
+    """(calls, {phase: summed ms}, {phase: launches per call}) since the last read."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    la = (ctypes.c_int32 * n)()
+    calls = load_library().letkf_phase_times(plan, ms, la, n)
+    if calls < 0:
+        raise LetkfError(-calls, "letkf_phase_times")
+    return calls, dict(zip(PHASES, list(ms))), dict(zip(PHASES, list(la)))
+
+
+def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
+    """a [batch, k, k] float64 -> lam [batch, k], vec [batch, k, k] (columns)."""
+    import torch
+    batch, k = int(a.shape[0]), int(a.shape[-1])
+    return _check(load_library().letkf_eigh_batched(
+        _ptr(a, torch.float64), batch, k, _ptr(lam, torch.float64), _ptr(vec, torch.float64),
+        _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
+        "letkf_eigh_batched")

@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+FP64 bar: relative L2 error of the analysis ensemble <= 1e-10 over every
+entry (whole fields on small grids, sampled points at full size), plus
+structural properties that hold at any size.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import letkf_oracle as orc
+from paper_2308_03310_amd import synth
+from paper_2308_03310_amd import letkf as L
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev_obs(p, torch):
+    f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+    return (f(p.obs_ix, torch.int32), f(p.obs_iy, torch.int32), f(p.obs_kind, torch.int32),
+            f(p.obs_val, torch.float64), f(p.obs_var, torch.float64))
+
+
+def gpu_analysis(p, L_len=None, infl=None, loc=L.LETKF_LOC_GAUSS, inplace=False, obs=True,
+                 var=None, xa_fill=None):
+    import torch
+    wl = p.wl
+    L_len = wl.L if L_len is None else L_len
+    infl = wl.infl if infl is None else infl
+    n_obs = len(p.obs_ix)
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, n_obs, L_len, infl, loc)])
+    try:
+        xb = torch.from_numpy(p.xb).cuda()
+        if inplace:
+            xa = xb
+        else:
+            xa = torch.full_like(xb, xa_fill) if xa_fill is not None else torch.empty_like(xb)
+        o = None
+        if obs:
+            o = list(dev_obs(p, torch))
+            if var is not None:
+                o[4] = torch.from_numpy(var).cuda()
+        L.letkf_analyze(plan, [L.make_io(0, xb, xa, o)])
+        st = L.letkf_status(plan, sync=True)
+        return xa.cpu().numpy(), st
+    finally:
+        L.letkf_plan_destroy(plan)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch(device):
+    import torch
+    return torch
+
+
+# ------------------------------------------------------------ eigensolver
+@pytest.mark.parametrize("k", [2, 3, 16, 17, 31, 32, 33, 48, 64])
+def test_eigh_batched_random(k):
+    import torch
+    say(f"eigh_batched k={k} batch=37")
+    rng = np.random.default_rng(100 + k)
+    B = rng.standard_normal((37, k, k))
+    A = B @ B.transpose(0, 2, 1) / k + np.eye(k) * (k - 1) / 1.1
+    A[5] = np.diag(rng.permutation(np.repeat([1.0, 2.0], (k + 1) // 2)[:k]))   # exact ties
+    A[6] = 3.0 * np.eye(k)
+    y = rng.standard_normal(k)
+    A[7] = 2.0 * np.eye(k) + np.outer(y, y)                                     # multiplicity k-1
+    A[8] = rng.standard_normal((k, k))
+    A[8] = A[8] + A[8].T                                                        # indefinite
+    a = torch.from_numpy(A).cuda()
+    lam = torch.empty(37, k, dtype=torch.float64, device="cuda")
+    vec = torch.empty(37, k, k, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L.letkf_eigh_batched(a, lam, vec, st)
+    torch.cuda.synchronize()
+    lam, vec = lam.cpu().numpy(), vec.cpu().numpy()
+    assert int(st.cpu()[0]) == 0
+    for i in range(37):
+        nrm = np.linalg.norm(A[i])
+        ref = np.linalg.eigvalsh(A[i])
+        np.testing.assert_allclose(np.sort(lam[i]), ref, rtol=0, atol=1e-13 * nrm)
+        V = vec[i]
+        assert np.linalg.norm(V @ np.diag(lam[i]) @ V.T - A[i]) <= 1e-13 * nrm * k
+        assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
+
+
+# ------------------------------------------------------------ whole analyses
+def _oracle_full(p, L_len=None, infl=None, loc=orc.LOC_GAUSS, var=None):
+    wl = p.wl
+    return orc.letkf_analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val,
+                              p.obs_var if var is None else var,
+                              wl.L if L_len is None else L_len, wl.infl if infl is None else infl,
+                              loc)
+
+
+def test_cpu32_k16_full_field():
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say("analysis cpu32_k16 (32x32, k=16) full field")
+    got, st = gpu_analysis(p)
+    assert st == L.LETKF_OK
+    ref = _oracle_full(p)
+    assert rel_l2(got, ref) <= TOL_FP64
+    inc = np.linalg.norm(got - ref) / np.linalg.norm(ref - p.xb)
+    assert inc <= 1e-9
+
+
+@pytest.mark.parametrize("loc", [orc.LOC_GAUSS, orc.LOC_GC, orc.LOC_NONE])
+@pytest.mark.parametrize("k", [5, 20, 40])
+def test_ragged_grid(loc, k):
+    """Grid and ensemble sizes that are not multiples of any tile: 40 x 27
+    lattice (ragged 64-point tiles and 8-point cells), obs of all three kinds
+    on a stride-3 mask, L = 3.3 (window wraps around the periodic box for
+    NONE)."""
+    wl = synth.Workload("ragged", 40, 27, k, 3, 0.01, 3.3, 1.15, 40 + k,
+                        kinds=(synth.OBS_RHO, synth.OBS_U, synth.OBS_V))
+    p = synth.make_problem(wl)
+    say(f"analysis ragged 40x27 k={k} loc={loc}")
+    got, st = gpu_analysis(p, loc=loc)
+    assert st == L.LETKF_OK
+    ref = _oracle_full(p, loc=loc)
+    assert rel_l2(got, ref) <= TOL_FP64
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref - p.xb) <= 1e-9
+
+
+def test_small_periodic_window_wraps():
+    """2L larger than half the box: windows wrap onto themselves; every
+    observation must be counted once at its minimum-image distance."""
+    wl = synth.Workload("wrap", 12, 10, 8, 2, 0.01, 3.0, 1.1, 9)
+    p = synth.make_problem(wl)
+    say("analysis wrap 12x10 k=8 L=3")
+    got, st = gpu_analysis(p)
+    assert st == L.LETKF_OK
+    assert rel_l2(got, _oracle_full(p)) <= TOL_FP64
+
+
+def test_inplace_and_determinism():
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say("analysis cpu32_k16 in-place vs out-of-place, twice")
+    a1, _ = gpu_analysis(p)
+    a2, _ = gpu_analysis(p)
+    a3, st = gpu_analysis(p, inplace=True)
+    assert st == L.LETKF_OK
+    assert np.array_equal(a1, a2)
+    assert np.array_equal(a1, a3)
+
+
+def test_infinite_variance_returns_inflated_background():
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say("analysis cpu32_k16 with every variance +inf")
+    var = np.full_like(p.obs_var, np.inf)
+    got, st = gpu_analysis(p, var=var)
+    assert st == L.LETKF_OK
+    xbar = p.xb.mean(axis=0, keepdims=True)
+    ref = xbar + math.sqrt(p.wl.infl) * (p.xb - xbar)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15)
+    got1, _ = gpu_analysis(p, var=var, infl=1.0)
+    np.testing.assert_allclose(got1, p.xb, rtol=0, atol=1e-15)
+
+
+def test_no_observations():
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say("analysis cpu32_k16 with n_obs = 0")
+    got, st = gpu_analysis(p, obs=False, infl=1.0)
+    assert st == L.LETKF_OK
+    np.testing.assert_allclose(got, p.xb, rtol=0, atol=1e-15)
+
+
+def test_invalid_observation_sets_status_and_skips():
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    for what in ("var_neg", "var_nan", "ix_range", "kind"):
+        q = synth.make_problem(p.wl)
+        if what == "var_neg":
+            q.obs_var = q.obs_var.copy(); q.obs_var[7] = -1.0
+        elif what == "var_nan":
+            q.obs_var = q.obs_var.copy(); q.obs_var[3] = np.nan
+        elif what == "ix_range":
+            q.obs_ix = q.obs_ix.copy(); q.obs_ix[11] = 32
+        else:
+            q.obs_kind = q.obs_kind.copy(); q.obs_kind[0] = 3
+        say(f"analysis cpu32_k16 with invalid observation ({what})")
+        got, st = gpu_analysis(q, xa_fill=-7.0)
+        assert st == L.LETKF_EINVAL
+        assert np.all(got == -7.0)
+    got, st = gpu_analysis(p)            # the plan's next call is clean again
+    assert st == L.LETKF_OK
+
+
+# ------------------------------------------------------------ full sizes, sampled
+@pytest.mark.parametrize("name,npts", [("grid256_k32", 48), ("grid1024_k64", 12)])
+def test_full_size_sampled(name, npts):
+    wl = synth.WORKLOADS[name]
+    say(f"generate {name}")
+    p = synth.make_problem(wl)
+    say(f"analysis {name} ({wl.nx}x{wl.ny}, k={wl.k}) on the GPU")
+    got, st = gpu_analysis(p)
+    assert st == L.LETKF_OK
+    # properties at every point: analysis perturbations sum to zero
+    mean = got.mean(axis=0, keepdims=True)
+    assert np.abs((got - mean).sum(axis=0)).max() <= 1e-14 * wl.k
+    assert np.isfinite(got).all()
+    pts = synth.sample_points(wl.nx, wl.ny, npts, seed=7)
+    say(f"oracle on {len(pts)} sampled points")
+    ref = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
+                       wl.infl).run(pts)
+    g = np.stack([got[:, :, q // wl.nx, q % wl.nx] for q in pts])
+    assert rel_l2(g, ref) <= TOL_FP64
+    xb = np.stack([p.xb[:, :, q // wl.nx, q % wl.nx] for q in pts])
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref - xb) <= 1e-9
