@@ -88,6 +88,8 @@ typedef struct letkf_problem {
 
 /* Plan flags. */
 #define LETKF_FLAG_PHASE_TIMING 1  /* record HIP events around every kernel phase */
+#define LETKF_FLAG_CYCLE        2  /* also allocate the lattice-BGK ping-pong buffer that
+                                      letkf_cycle needs (one ensemble per problem) */
 
 /* Plan options (pass NULL for the defaults: no budget, no flags). */
 typedef struct letkf_options {
@@ -136,9 +138,12 @@ typedef struct letkf_io {
 int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream);
 
 /* One data-assimilation cycle (Sec. II-B, DA cycle steps 2-3): n_steps
- * lattice-BGK steps with relaxation time tau and a Kolmogorov body force
- * F_x(y) = force_amp * sin(2 pi force_kx y / ny), then one analysis.  The
- * ensemble is advanced and analysed in place: io.xa must equal io.xb. */
+ * lattice-BGK steps (the lattice Boltzmann equation of Sec. II-A, collide
+ * then stream, single relaxation time tau) with a Kolmogorov body force
+ * F_x(y) = force_amp * sin(2 pi force_kx y / ny), F_y = 0, added as the
+ * source 3 w_i (c_i . F) after relaxation; then one analysis.  The ensemble
+ * is advanced and analysed in place: io.xa must equal io.xb.  The plan must
+ * have been made with LETKF_FLAG_CYCLE (else LETKF_EINVAL). */
 typedef struct letkf_cycle_io {
   letkf_io io;
   int32_t  n_steps;    /* >= 0 */

@@ -41,6 +41,7 @@ struct ProblemWs {
   double* rinv;
   double* C;
   double* b;
+  double* bgk;   // lattice-BGK ping-pong buffer (plans made with LETKF_FLAG_CYCLE)
 };
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -142,7 +143,10 @@ uint64_t ws_bytes(const ProblemWs& w) {
   return b;
 }
 
-int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool timed) {
+// src: member-major background to analyse (io.xb unless a cycle left it in
+// the ping-pong buffer).
+int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool timed,
+                     const double* src) {
   ProblemWs& w = pl->probs[io.problem];
   const letkf_problem& p = w.p;
   const int k = p.k;
@@ -194,7 +198,7 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
 
   if (launch_bin(oa, s) != hipSuccess) return LETKF_EDEVICE;
   mark(1);
-  if (launch_transpose_in(io.xb, w.xt, k, w.npts, abort_flag, s) != hipSuccess) return LETKF_EDEVICE;
+  if (launch_transpose_in(src, w.xt, k, w.npts, abort_flag, s) != hipSuccess) return LETKF_EDEVICE;
   mark(2);
   if (launch_obs_operator(oa, s) != hipSuccess) return LETKF_EDEVICE;
   mark(3);
@@ -296,7 +300,8 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
                letkf_plan_t* out) {
   if (out) *out = nullptr;
   if (!out || !probs || n_probs < 1) return LETKF_EINVAL;
-  if (opt && (opt->flags & ~LETKF_FLAG_PHASE_TIMING) != 0) return LETKF_EINVAL;
+  if (opt && (opt->flags & ~(LETKF_FLAG_PHASE_TIMING | LETKF_FLAG_CYCLE)) != 0) return LETKF_EINVAL;
+  const bool cycle = opt && (opt->flags & LETKF_FLAG_CYCLE);
   for (int i = 0; i < n_probs; ++i) {
     const int rc = check_problem(probs[i]);
     if (rc != LETKF_OK) return rc;
@@ -308,6 +313,7 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     ws[i].p = probs[i];
     plan_sizes(ws[i]);
     total += ws_bytes(ws[i]);
+    if (cycle) total += (uint64_t)ws[i].npts * 9 * probs[i].k * sizeof(double);
   }
   if (opt && opt->hbm_budget_bytes && total > opt->hbm_budget_bytes) return LETKF_ENOMEM;
   int dev = 0;
@@ -329,6 +335,7 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     ok = ok && pl->alloc(&w.cell_count, w.ncells) && pl->alloc(&w.cell_start, w.ncells + 1) &&
          pl->alloc(&w.cell_fill, w.ncells);
     ok = ok && pl->alloc(&w.C, (size_t)w.chunk * w.nb * 256) && pl->alloc(&w.b, (size_t)w.chunk * w.kp);
+    if (cycle) ok = ok && pl->alloc(&w.bgk, (size_t)w.npts * 9 * k);
     if (!ok) break;
   }
   if (ok && opt && (opt->flags & LETKF_FLAG_PHASE_TIMING)) {
@@ -362,18 +369,46 @@ int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   int rc = LETKF_OK;
   for (int i = 0; i < n_io && rc == LETKF_OK; ++i)
-    rc = enqueue_analysis(plan, io[i], s, plan->timing && i == 0);
+    rc = enqueue_analysis(plan, io[i], s, plan->timing && i == 0, io[i].xb);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;
 }
 
 int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream) {
-  (void)plan;
-  (void)io;
-  (void)n_io;
-  (void)hip_stream;
-  return LETKF_EINVAL;
+  if (!plan || !io || n_io < 0) return LETKF_EINVAL;
+  for (int i = 0; i < n_io; ++i) {
+    const int rc = check_io(plan, io[i].io);
+    if (rc != LETKF_OK) return rc;
+    if (io[i].io.xa != io[i].io.xb || io[i].n_steps < 0) return LETKF_EINVAL;
+    if (!(io[i].tau > 0.5) || !std::isfinite(io[i].tau) || !std::isfinite(io[i].force_amp))
+      return LETKF_EINVAL;
+    if (io[i].n_steps > 0 && !plan->probs[io[i].io.problem].bgk) return LETKF_EINVAL;
+  }
+  int expect = 0;
+  if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int rc = LETKF_OK;
+  for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
+    const letkf_cycle_io& c = io[i];
+    ProblemWs& w = plan->probs[c.io.problem];
+    // ping-pong between the caller's ensemble and the plan's buffer
+    double* cur = const_cast<double*>(c.io.xb);
+    double* nxt = w.bgk;
+    for (int st = 0; st < c.n_steps && rc == LETKF_OK; ++st) {
+      if (launch_bgk(cur, nxt, w.p.k, w.p.nx, w.p.ny, c.tau, c.force_amp, c.force_kx, s) !=
+          hipSuccess)
+        rc = LETKF_EDEVICE;
+      double* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    if (rc == LETKF_OK) rc = enqueue_analysis(plan, c.io, s, plan->timing && i == 0, cur);
+  }
+  plan->last_stream = s;
+  plan->busy.store(0);
+  return rc;
 }
 
 int letkf_status(letkf_plan_t plan, int32_t sync) {

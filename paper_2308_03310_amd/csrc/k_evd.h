@@ -147,38 +147,129 @@ __device__ __forceinline__ bool jacobi_solve(double (&a)[KP], double (&v)[KP], i
   }
 }
 
-// LDS per wavefront: matrix area (input staging, rotation coefficients
-// during the sweeps, then V in natural layout) and a 5 x KP area per matrix
-// that holds b, then Lambda^-1 V^T b, then dX and dX V for up to five of the
-// nine components at a time.  One-wavefront blocks at KP = 32 then use
-// 18.4 KiB, so eight fit in a CU's 160 KiB.
+// ---- split solve: wavefront 0 holds A and computes the rotations, wavefront
+// 1 holds V and applies them; one workgroup barrier per round publishes the
+// coefficient buffer.  Used for 64-row matrices, whose A and V rows (2 x 128
+// VGPRs) do not fit one wavefront's registers.
+__device__ __forceinline__ void block_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int opaque_lane(int jj) {
+  int jr;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(jr) : "v"(jj));
+  return jr;
+}
+
+template <int KP, int M, int U>
+__device__ __forceinline__ void jacobi_pair_a(double (&a)[KP], int jj, double c, double sr,
+                                              const double2* cb) {
+  constexpr int UM = U ^ M;
+  const double pu = xor_lane<M>(a[UM]);
+  const double pum = xor_lane<M>(a[U]);
+  const double x0 = fma(sr, pu, c * a[U]);
+  const double x1 = fma(sr, pum, c * a[UM]);
+  const double2 cf = cb[jj ^ U];
+  a[U] = fma(cf.y, x1, cf.x * x0);
+  a[UM] = fma(-cf.y, x0, cf.x * x1);
+}
+
+template <int R>
+__device__ __forceinline__ void v_pair_fence() {
+  if constexpr (R % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int KP, int M, int U>
+__device__ __forceinline__ void jacobi_pair_v(double (&v)[KP], int jj, const double2* cb) {
+  constexpr int UM = U ^ M;
+  const double2 cf = cb[jj ^ U];
+  const double v0 = v[U], v1 = v[UM];
+  v[U] = fma(cf.y, v1, cf.x * v0);
+  v[UM] = fma(-cf.y, v0, cf.x * v1);
+}
+
+template <int KP, int M, int... Rs>
+__device__ __forceinline__ void jacobi_round_a(double (&a)[KP], int jj, double2* cb,
+                                               std::integer_sequence<int, Rs...>) {
+  constexpr int HB = high_bit<M>();
+  const bool lo = (jj & HB) == 0;
+  const double d_self = a[0];
+  const double d_oth = xor_lane<M>(d_self);
+  const double o_self = a[M];
+  const double o_oth = xor_lane<M>(o_self);
+  const double app = lo ? d_self : d_oth;
+  const double aqq = lo ? d_oth : d_self;
+  const double apq = lo ? o_self : o_oth;
+  const bool nz = apq != 0.0;
+  const double zeta = (aqq - app) / (2.0 * (nz ? apq : 1.0));
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+  const double t = nz ? tt : 0.0;
+  const double c = rsqrt(fma(t, t, 1.0));
+  const double s = t * c;
+  const double sr = lo ? -s : s;
+  cb[jj] = make_double2(c, sr);
+  block_sync();
+  const int jr = opaque_lane(jj);
+  (jacobi_pair_a<KP, M, rep_slot<M, Rs>()>(a, jr, c, sr, cb), ...);
+  a[0] = lo ? fma(-t, apq, app) : fma(t, apq, aqq);
+  a[M] = 0.0;
+}
+
+template <int KP, int M, int... Rs>
+__device__ __forceinline__ void jacobi_round_v(double (&v)[KP], int jj, const double2* cb,
+                                               std::integer_sequence<int, Rs...>) {
+  block_sync();
+  const int jr = opaque_lane(jj);
+  // fences every 8 pairs: otherwise all KP/2 coefficient loads of the round
+  // are hoisted and live next to V's own 2*KP registers
+  ((jacobi_pair_v<KP, M, rep_slot<M, Rs>()>(v, jr, cb), v_pair_fence<Rs>()), ...);
+}
+
+template <int KP, int... Ms>
+__device__ __forceinline__ void jacobi_sweep_a(double (&a)[KP], int jj, double2* cb0, double2* cb1,
+                                               std::integer_sequence<int, Ms...>) {
+  (jacobi_round_a<KP, Ms + 1>(a, jj, (Ms & 1) ? cb1 : cb0,
+                              std::make_integer_sequence<int, KP / 2>{}), ...);
+}
+
+template <int KP, int... Ms>
+__device__ __forceinline__ void jacobi_sweep_v(double (&v)[KP], int jj, const double2* cb0,
+                                               const double2* cb1,
+                                               std::integer_sequence<int, Ms...>) {
+  (jacobi_round_v<KP, Ms + 1>(v, jj, (Ms & 1) ? cb1 : cb0,
+                              std::make_integer_sequence<int, KP / 2>{}), ...);
+}
+
+// LDS per block: matrix area (input staging, rotation coefficients during
+// the sweeps, then V in natural layout, row stride KP+1) and a 5 x KP area
+// per matrix that holds b, then Lambda^-1 V^T b, then dX and dX V for up to
+// five of the nine components at a time.  One-wavefront blocks at KP = 32
+// use 19 KiB, so eight fit in a CU's 160 KiB.
 constexpr int kCompGroup = 5;
 template <int KP>
 struct EvdLds {
   static constexpr int G = 64 / KP;
-  double mat[G][KP * KP];
+  static constexpr int S = KP + 1;   // row stride: 16 consecutive rows hit distinct banks
+  double mat[G][KP * S];
   double dxu[G][kCompGroup][KP];
+  double lam[64];
+  int flag;
 };
 
-// mode 0: LETKF transform + update of the point-major ensemble (EvdArgs
-//         fields C, b, xt); mode 1: standalone batched eigensolve (A, lam, vec).
+// Q = alpha I + C (mode 0, upper blocks mirrored) or A (mode 1) into the
+// matrix area, padded rows = unit; b into dxu[0] (mode 0).
 template <int KP>
-__global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
-  constexpr int G = 64 / KP;
+__device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
+                                             int pl, bool valid) {
   constexpr int NQ = KP / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
-  __shared__ EvdLds<KP> sh;
-  if (e.abort_flag && *e.abort_flag) return;
-  const int lane = lane_id();
-  const int seg = lane / KP, jj = lane % KP;
-  const int pl = blockIdx.x * G + seg;
-  const bool valid = pl < e.npt;
+  constexpr int S = EvdLds<KP>::S;
   const int k = e.k;
   double* M = sh.mat[seg];
-
   if (e.mode == 0) {
-    // Q = alpha I + C in LDS (upper blocks mirrored), padded rows = unit
-    for (int c = 0; c < KP; ++c) M[jj * KP + c] = 0.0;
+    for (int c = 0; c < KP; ++c) M[jj * S + c] = 0.0;
     wave_lds_sync();
     if (valid) {
       const double* Cp = e.C + (size_t)pl * NB * 256;
@@ -190,8 +281,8 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
           for (int t = jj; t < 256; t += KP) {
             const int r = t >> 4, c = t & 15;
             const double val = Cp[blk * 256 + t];
-            M[(16 * I + r) * KP + 16 * J + c] = val;
-            if (I != J) M[(16 * J + c) * KP + 16 * I + r] = val;
+            M[(16 * I + r) * S + 16 * J + c] = val;
+            if (I != J) M[(16 * J + c) * S + 16 * I + r] = val;
           }
           ++blk;
         }
@@ -199,64 +290,83 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
     }
     wave_lds_sync();
     if (valid && jj < k)
-      M[jj * KP + jj] += e.alpha;
+      M[jj * S + jj] += e.alpha;
     else
-      M[jj * KP + jj] = 1.0;
+      M[jj * S + jj] = 1.0;
     sh.dxu[seg][0][jj] = (valid && jj < k) ? e.b[(size_t)pl * KP + jj] : 0.0;
   } else {
-    // A[pl] (upper triangle) with unit padding
     for (int c = 0; c < KP; ++c) {
       double val = c == jj ? 1.0 : 0.0;
       if (valid && jj < k && c < k) {
         const int r0 = jj < c ? jj : c, c0 = jj < c ? c : jj;
         val = e.A[((size_t)pl * k + r0) * k + c0];
       }
-      M[jj * KP + c] = val;
+      M[jj * S + c] = val;
     }
   }
-  wave_lds_sync();
+}
 
-  double a[KP], v[KP];
+template <int KP>
+__device__ __forceinline__ void load_rows(const double* M, int jj, double (&a)[KP]) {
+  constexpr int S = KP + 1;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) a[u] = M[jj * S + (jj ^ u)];
+}
+
+// Diagonal-layout rows (v[u] = V[jj][jj^u]) into the natural layout in LDS.
+template <int KP>
+__device__ __forceinline__ void store_rows(double* M, int jj, const double (&v)[KP]) {
+  constexpr int S = KP + 1;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) M[jj * S + (jj ^ u)] = v[u];
+}
+
+template <int KP>
+__device__ __forceinline__ void init_identity(double (&v)[KP]) {
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
-    a[u] = M[jj * KP + (jj ^ u)];
-    v[u] = u == 0 ? 1.0 : 0.0;
+    // opaque constants: the compiler must not specialize the first sweep for V = I
+    double x = u == 0 ? 1.0 : 0.0;
+    asm volatile("" : "+v"(x));
+    v[u] = x;
   }
-  wave_lds_sync();
+}
 
-  // eigensolve; the matrix area holds the rotation coefficients meanwhile
-  double2* cb0 = reinterpret_cast<double2*>(M);
-  double2* cb1 = cb0 + KP;
-  const bool conv = jacobi_solve<KP>(a, v, jj, cb0, cb1, e.tol2, e.max_sweeps);
-  if (!conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
-  wave_lds_sync();
-  const double lam = a[0];
-
-  // V in natural layout: M[r][c] = V[r][c]
-#pragma unroll
-  for (int u = 0; u < KP; ++u) M[jj * KP + (jj ^ u)] = v[u];
-  wave_lds_sync();
-
-  if (e.mode != 0) {
-    if (valid && jj < k) {
-      e.lam[(size_t)pl * k + jj] = lam;
-      for (int r = 0; r < k; ++r) e.vec[((size_t)pl * k + r) * k + jj] = M[r * KP + jj];
-    }
-    return;
+// Mode 1 output: eigenvalues and eigenvectors (V natural layout in M).
+template <int KP>
+__device__ __forceinline__ void write_eig(const EvdArgs& e, const double* M, int jj, int pl,
+                                          bool valid, double lam) {
+  const int k = e.k;
+  if (valid && jj < k) {
+    e.lam[(size_t)pl * k + jj] = lam;
+    for (int r = 0; r < k; ++r) e.vec[((size_t)pl * k + r) * k + jj] = M[r * (KP + 1) + jj];
   }
+}
 
+// Mode 0: transform and in-place update of the point's nine components,
+// from V (natural layout in M, row stride KP+1), this lane's eigenvalue lam
+// and b (in dxu[0]).  Row reads M[jj][c] and column reads M[m][jj] are both
+// bank-conflict free within 16-lane groups.
+template <int KP>
+__device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
+                                                 int pl, bool valid, double lam) {
+  constexpr int S = KP + 1;
+  const int k = e.k;
+  const double* M = sh.mat[seg];
+  const double* Mrow = M + jj * S;
   // z = Lambda^-1 V^T b  (lane jj = column jj)
   double* bz = sh.dxu[seg][0];
   double z = 0.0;
-  for (int r = 0; r < KP; ++r) z = fma(M[r * KP + jj], bz[r], z);
+#pragma unroll 4
+  for (int r = 0; r < KP; ++r) z = fma(M[r * S + jj], bz[r], z);
   z /= lam;
   wave_lds_sync();
   bz[jj] = z;
   wave_lds_sync();
   // wbar = V z  (lane jj = row jj)
   double wb = 0.0;
-#pragma unroll
-  for (int u = 0; u < KP; ++u) wb = fma(v[u], bz[jj ^ u], wb);
+#pragma unroll 4
+  for (int c = 0; c < KP; ++c) wb = fma(Mrow[c], bz[c], wb);
   wave_lds_sync();
 
   // the point's nine components: mean and perturbations (eqs. xmean, xspread)
@@ -284,8 +394,9 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
     double U[CG];
 #pragma unroll
     for (int i = 0; i < CG; ++i) U[i] = 0.0;
+#pragma unroll 2
     for (int m = 0; m < KP; ++m) {
-      const double vm = M[m * KP + jj];
+      const double vm = M[m * S + jj];
 #pragma unroll
       for (int i = 0; i < CG; ++i)
         if (i < nc) U[i] = fma(sh.dxu[seg][i][m], vm, U[i]);
@@ -296,13 +407,20 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
       if (i < nc) sh.dxu[seg][i][jj] = U[i] * d2;
     wave_lds_sync();
     // X^a = xbar + dX wbar + U V^T   (lane jj = member jj)
+    double acc[CG];
+#pragma unroll
+    for (int i = 0; i < CG; ++i) acc[i] = 0.0;
+#pragma unroll 2
+    for (int c = 0; c < KP; ++c) {
+      const double vr = Mrow[c];
+#pragma unroll
+      for (int i = 0; i < CG; ++i)
+        if (i < nc) acc[i] = fma(sh.dxu[seg][i][c], vr, acc[i]);
+    }
 #pragma unroll
     for (int i = 0; i < CG; ++i) {
       if (i >= nc) break;
-      double acc = 0.0;
-#pragma unroll
-      for (int u = 0; u < KP; ++u) acc = fma(sh.dxu[seg][i][jj ^ u], v[u], acc);
-      const double xa = xbar[i] + (sm[i] + acc);
+      const double xa = xbar[i] + (sm[i] + acc[i]);
       finite = finite && __builtin_isfinite(xa);
       if (mine) xp[(i0 + i) * k] = xa;
     }
@@ -311,10 +429,105 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
   if (mine && !finite) atomicOr(e.status, kStatNonfinite);
 }
 
+// One wavefront holds both A and V rows of 64/KP matrices (KP = 16, 32).
+template <int KP>
+__global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
+  constexpr int G = 64 / KP;
+  __shared__ EvdLds<KP> sh;
+  if (e.abort_flag && *e.abort_flag) return;
+  const int lane = lane_id();
+  const int seg = lane / KP, jj = lane % KP;
+  const int pl = blockIdx.x * G + seg;
+  const bool valid = pl < e.npt;
+  double* M = sh.mat[seg];
+  stage_matrix<KP>(e, sh, seg, jj, pl, valid);
+  wave_lds_sync();
+  double a[KP], v[KP];
+  load_rows<KP>(M, jj, a);
+  init_identity<KP>(v);
+  wave_lds_sync();
+  double2* cb0 = reinterpret_cast<double2*>(M);
+  const bool conv = jacobi_solve<KP>(a, v, jj, cb0, cb0 + KP, e.tol2, e.max_sweeps);
+  if (!conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
+  wave_lds_sync();
+  const double lam = a[0];
+  store_rows<KP>(M, jj, v);
+  wave_lds_sync();
+  if (e.mode != 0) {
+    write_eig<KP>(e, M, jj, pl, valid, lam);
+    return;
+  }
+  transform_update<KP>(e, sh, seg, jj, pl, valid, lam);
+}
+
+// Two wavefronts per block: wavefront 0 holds A (and ends with the
+// eigenvalues), wavefront 1 holds V and does the transform.
+template <int KP>
+__global__ __launch_bounds__(128) void k_evd_split(EvdArgs e) {
+  constexpr int G = 64 / KP;
+  __shared__ EvdLds<KP> sh;
+  if (e.abort_flag && *e.abort_flag) return;
+  // wave-uniform role (readfirstlane makes the branch provably uniform, so A
+  // and V never share one wavefront's registers)
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = lane_id();
+  const int seg = lane / KP, jj = lane % KP;
+  const int pl = blockIdx.x * G + seg;
+  const bool valid = pl < e.npt;
+  double* M = sh.mat[seg];
+  if (wid == 0) stage_matrix<KP>(e, sh, seg, jj, pl, valid);
+  block_sync();
+  double2* cb0 = reinterpret_cast<double2*>(M);
+  double2* cb1 = cb0 + KP;
+  double lam = 1.0;
+  if (wid == 0) {
+    double a[KP];
+    load_rows<KP>(M, jj, a);
+    block_sync();                                  // matrix area becomes the coefficient buffers
+    for (int sweep = 0;; ++sweep) {
+      double off = 0.0;
+#pragma unroll
+      for (int u = 1; u < KP; ++u) off = fma(a[u], a[u], off);
+      const double dg = a[0] * a[0];
+      const bool conv = group_sum<KP>(off) <= e.tol2 * group_sum<KP>(dg);
+      const bool all = __ballot(!conv) == 0;
+      const bool stop = all || sweep >= e.max_sweeps;
+      if (stop && !all && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
+      if (lane == 0) sh.flag = stop ? 1 : 0;
+      block_sync();
+      if (stop) break;
+      jacobi_sweep_a<KP>(a, jj, cb0, cb1, std::make_integer_sequence<int, KP - 1>{});
+    }
+    lam = a[0];
+    sh.lam[lane] = lam;
+    block_sync();                                  // V written by wavefront 1
+    block_sync();                                  // eigenvalues published
+    if (e.mode != 0) write_eig<KP>(e, M, jj, pl, valid, lam);
+  } else {
+    double v[KP];
+    init_identity<KP>(v);
+    block_sync();
+    for (;;) {
+      block_sync();
+      if (sh.flag) break;
+      jacobi_sweep_v<KP>(v, jj, cb0, cb1, std::make_integer_sequence<int, KP - 1>{});
+    }
+    store_rows<KP>(M, jj, v);
+    block_sync();
+    block_sync();
+    lam = sh.lam[lane];
+    if (e.mode == 0) transform_update<KP>(e, sh, seg, jj, pl, valid, lam);
+  }
+}
+
 template <int KP>
 hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s) {
-  const dim3 grid(ceil_div(a.npt, 64 / KP)), block(64);
-  hipLaunchKernelGGL(k_evd<KP>, grid, block, 0, s, a);
+  const dim3 grid(ceil_div(a.npt, 64 / KP));
+  if constexpr (KP == 64) {
+    hipLaunchKernelGGL(k_evd_split<KP>, grid, dim3(128), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_evd<KP>, grid, dim3(64), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -85,6 +85,8 @@ hipError_t launch_obs_operator(const ObsArgs& a, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int kp, hipStream_t s);
 template <int KP>
 hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s);
+hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
+                      int force_kx, hipStream_t s);
 
 inline int pow2_at_least16(int k) {
   int p = 16;

@@ -24,6 +24,7 @@ LETKF_PREC_FP64, LETKF_PREC_FP32, LETKF_PREC_BF16 = 0, 1, 2
 LETKF_OBS_RHO, LETKF_OBS_U, LETKF_OBS_V = 0, 1, 2
 LETKF_MAX_K = 64
 LETKF_FLAG_PHASE_TIMING = 1
+LETKF_FLAG_CYCLE = 2
 PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose")
 
 
@@ -171,6 +172,13 @@ def letkf_analyze(plan: int, ios: Iterable[letkf_io], stream=None) -> int:
     arr = (letkf_io * len(ios))(*ios)
     return _check(load_library().letkf_analyze(plan, arr, len(ios), _stream(stream)),
                   "letkf_analyze")
+
+
+def make_cycle_io(problem: int, x, obs=None, n_steps: int = 50, tau: float = 0.52,
+                  force_amp: float = 1e-5, force_kx: int = 4) -> letkf_cycle_io:
+    """In-place cycle descriptor for ensemble x (advanced, then analysed)."""
+    return letkf_cycle_io(make_io(problem, x, x, obs), int(n_steps), int(force_kx), float(tau),
+                          float(force_amp))
 
 
 def letkf_cycle(plan: int, ios: Iterable[letkf_cycle_io], stream=None) -> int:
