@@ -36,7 +36,8 @@ struct ProblemWs {
   int* cell_fill;
   int* ox;
   int* oy;
-  double* Yb;
+  double* Yb;    // FP64 perturbations (FP64 form)
+  void* Ylp;     // FP32 / BF16 perturbations (reduced forms)
   double* d;
   double* rinv;
   double* C;
@@ -53,7 +54,9 @@ int check_problem(const letkf_problem& p) {
   if (!finite_pos(p.loc_len) || !finite_pos(p.infl)) return LETKF_EINVAL;
   if (p.loc != LETKF_LOC_GAUSS && p.loc != LETKF_LOC_GC && p.loc != LETKF_LOC_NONE)
     return LETKF_EINVAL;
-  if (p.precision != LETKF_PREC_FP64) return LETKF_EINVAL;  // reduced forms not built yet
+  if (p.precision != LETKF_PREC_FP64 && p.precision != LETKF_PREC_FP32 &&
+      p.precision != LETKF_PREC_BF16)
+    return LETKF_EINVAL;
   return LETKF_OK;
 }
 
@@ -137,7 +140,8 @@ void plan_sizes(ProblemWs& w) {
 uint64_t ws_bytes(const ProblemWs& w) {
   const uint64_t no = (uint64_t)w.nobs_alloc;
   uint64_t b = (uint64_t)w.npts * 9 * w.p.k * sizeof(double);
-  b += no * 5 * sizeof(int) + no * (w.kp + 2) * sizeof(double);
+  const uint64_t ybytes = w.p.precision == LETKF_PREC_FP64 ? 8 : (w.p.precision == LETKF_PREC_FP32 ? 4 : 2);
+  b += no * 5 * sizeof(int) + no * w.kp * ybytes + no * 2 * sizeof(double);
   b += (uint64_t)(3 * w.ncells + 1) * sizeof(int);
   b += (uint64_t)w.chunk * (w.nb * 256 + w.kp) * sizeof(double);
   return b;
@@ -190,6 +194,8 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
   oa.ox = w.ox;
   oa.oy = w.oy;
   oa.Yb = w.Yb;
+  oa.Ylp = w.Ylp;
+  oa.prec = p.precision;
   oa.d = w.d;
   oa.rinv = w.rinv;
   oa.xt = w.xt;
@@ -226,6 +232,7 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
   ga.ox = w.ox;
   ga.oy = w.oy;
   ga.Yb = w.Yb;
+  ga.Ylp = w.Ylp;
   ga.d = w.d;
   ga.rinv = w.rinv;
   ga.C = w.C;
@@ -234,6 +241,7 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
 
   EvdArgs ea{};
   ea.mode = 0;
+  ea.prec = p.precision;
   ea.k = k;
   ea.npts = w.npts;
   ea.alpha = (double)(k - 1) / p.infl;
@@ -251,7 +259,9 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
     const int n = (w.npts - pt0) < w.chunk ? (w.npts - pt0) : w.chunk;
     ga.pt0 = pt0;
     ga.npt = n;
-    if (launch_gram_f64(ga, w.kp, s) != hipSuccess) return LETKF_EDEVICE;
+    const hipError_t ge = p.precision == LETKF_PREC_FP64 ? launch_gram_f64(ga, w.kp, s)
+                                                         : launch_gram_lp(ga, w.kp, p.precision, s);
+    if (ge != hipSuccess) return LETKF_EDEVICE;
     mark(4 + 2 * ci);
     ea.pt0 = pt0;
     ea.npt = n;
@@ -331,7 +341,14 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     ok = ok && pl->alloc(&w.xt, (size_t)w.npts * 9 * k);
     ok = ok && pl->alloc(&w.obs_cell, no) && pl->alloc(&w.perm, no) && pl->alloc(&w.ox, no) &&
          pl->alloc(&w.oy, no);
-    ok = ok && pl->alloc(&w.Yb, no * w.kp) && pl->alloc(&w.d, no) && pl->alloc(&w.rinv, no);
+    if (w.p.precision == LETKF_PREC_FP64) {
+      ok = ok && pl->alloc(&w.Yb, no * w.kp);
+    } else {
+      unsigned char* q = nullptr;
+      ok = ok && pl->alloc(&q, no * w.kp * (w.p.precision == LETKF_PREC_FP32 ? 4 : 2));
+      w.Ylp = q;
+    }
+    ok = ok && pl->alloc(&w.d, no) && pl->alloc(&w.rinv, no);
     ok = ok && pl->alloc(&w.cell_count, w.ncells) && pl->alloc(&w.cell_start, w.ncells + 1) &&
          pl->alloc(&w.cell_fill, w.ncells);
     ok = ok && pl->alloc(&w.C, (size_t)w.chunk * w.nb * 256) && pl->alloc(&w.b, (size_t)w.chunk * w.kp);

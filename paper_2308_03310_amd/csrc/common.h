@@ -82,4 +82,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// bfloat16 <-> float, round to nearest even (finite values).
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+// Operand rounding of the reduced-precision forms: prec 1 = FP32, 2 = BF16.
+__device__ __forceinline__ float round_operand(double x, int prec) {
+  const float f = (float)x;
+  return prec == 2 ? from_bf16(to_bf16(f)) : f;
+}
+
 }  // namespace letkf

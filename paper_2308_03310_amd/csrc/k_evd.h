@@ -347,26 +347,39 @@ __device__ __forceinline__ void write_eig(const EvdArgs& e, const double* M, int
 // from V (natural layout in M, row stride KP+1), this lane's eigenvalue lam
 // and b (in dxu[0]).  Row reads M[jj][c] and column reads M[m][jj] are both
 // bank-conflict free within 16-lane groups.
-template <int KP>
+// T = double: FP64 contractions.  T = float: the reduced-precision forms —
+// V, b, dX, U and the weights are rounded to FP32 or BF16 (e.prec) as
+// contraction operands and accumulated in FP32; the ensemble mean, its
+// subtraction and the eigenvalue scaling stay FP64.
+template <typename T>
+__device__ __forceinline__ T opnd(double x, int prec);
+template <>
+__device__ __forceinline__ double opnd<double>(double x, int) { return x; }
+template <>
+__device__ __forceinline__ float opnd<float>(double x, int prec) { return round_operand(x, prec); }
+
+template <int KP, typename T>
 __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
                                                  int pl, bool valid, double lam) {
+  const int prec = e.prec;
   constexpr int S = KP + 1;
   const int k = e.k;
   const double* M = sh.mat[seg];
   const double* Mrow = M + jj * S;
   // z = Lambda^-1 V^T b  (lane jj = column jj)
   double* bz = sh.dxu[seg][0];
-  double z = 0.0;
+  T z = 0;
 #pragma unroll 4
-  for (int r = 0; r < KP; ++r) z = fma(M[r * S + jj], bz[r], z);
-  z /= lam;
+  for (int r = 0; r < KP; ++r) z = fma(opnd<T>(M[r * S + jj], prec), opnd<T>(bz[r], prec), z);
+  const double z1 = (double)z / lam;
   wave_lds_sync();
-  bz[jj] = z;
+  bz[jj] = z1;
   wave_lds_sync();
   // wbar = V z  (lane jj = row jj)
-  double wb = 0.0;
+  T wbt = 0;
 #pragma unroll 4
-  for (int c = 0; c < KP; ++c) wb = fma(Mrow[c], bz[c], wb);
+  for (int c = 0; c < KP; ++c) wbt = fma(opnd<T>(Mrow[c], prec), opnd<T>(bz[c], prec), wbt);
+  const T wb = opnd<T>((double)wbt, prec);
   wave_lds_sync();
 
   // the point's nine components: mean and perturbations (eqs. xmean, xspread)
@@ -379,48 +392,50 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
   for (int i0 = 0; i0 < 9; i0 += kCompGroup) {
     constexpr int CG = kCompGroup;
     const int nc = 9 - i0 < CG ? 9 - i0 : CG;
-    double dx[CG], xbar[CG], sm[CG];
+    double dx[CG], xbar[CG];
+    T sm[CG];
 #pragma unroll
     for (int i = 0; i < CG; ++i) {
       if (i >= nc) break;
       dx[i] = mine ? xp[(i0 + i) * k] : 0.0;
       xbar[i] = group_sum<KP>(dx[i]) * inv_k;
       dx[i] = mine ? dx[i] - xbar[i] : 0.0;
-      sm[i] = group_sum<KP>(dx[i] * wb);  // (dX wbar)_i
-      sh.dxu[seg][i][jj] = dx[i];
+      const T dxo = opnd<T>(dx[i], prec);
+      sm[i] = (T)group_sum<KP>((double)(dxo * wb));  // (dX wbar)_i
+      sh.dxu[seg][i][jj] = (double)dxo;
     }
     wave_lds_sync();
     // U = dX V diag(sqrt(k-1) lam^-1/2)   (lane jj = column jj)
-    double U[CG];
+    T U[CG];
 #pragma unroll
-    for (int i = 0; i < CG; ++i) U[i] = 0.0;
+    for (int i = 0; i < CG; ++i) U[i] = 0;
 #pragma unroll 2
     for (int m = 0; m < KP; ++m) {
-      const double vm = M[m * S + jj];
+      const T vm = opnd<T>(M[m * S + jj], prec);
 #pragma unroll
       for (int i = 0; i < CG; ++i)
-        if (i < nc) U[i] = fma(sh.dxu[seg][i][m], vm, U[i]);
+        if (i < nc) U[i] = fma((T)sh.dxu[seg][i][m], vm, U[i]);
     }
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < CG; ++i)
-      if (i < nc) sh.dxu[seg][i][jj] = U[i] * d2;
+      if (i < nc) sh.dxu[seg][i][jj] = (double)opnd<T>((double)U[i] * d2, prec);
     wave_lds_sync();
     // X^a = xbar + dX wbar + U V^T   (lane jj = member jj)
-    double acc[CG];
+    T acc[CG];
 #pragma unroll
-    for (int i = 0; i < CG; ++i) acc[i] = 0.0;
+    for (int i = 0; i < CG; ++i) acc[i] = 0;
 #pragma unroll 2
     for (int c = 0; c < KP; ++c) {
-      const double vr = Mrow[c];
+      const T vr = opnd<T>(Mrow[c], prec);
 #pragma unroll
       for (int i = 0; i < CG; ++i)
-        if (i < nc) acc[i] = fma(sh.dxu[seg][i][c], vr, acc[i]);
+        if (i < nc) acc[i] = fma((T)sh.dxu[seg][i][c], vr, acc[i]);
     }
 #pragma unroll
     for (int i = 0; i < CG; ++i) {
       if (i >= nc) break;
-      const double xa = xbar[i] + (sm[i] + acc[i]);
+      const double xa = xbar[i] + (double)(sm[i] + acc[i]);
       finite = finite && __builtin_isfinite(xa);
       if (mine) xp[(i0 + i) * k] = xa;
     }
@@ -457,7 +472,10 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
     write_eig<KP>(e, M, jj, pl, valid, lam);
     return;
   }
-  transform_update<KP>(e, sh, seg, jj, pl, valid, lam);
+  if (e.prec == 0)
+    transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam);
+  else
+    transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam);
 }
 
 // Two wavefronts per block: wavefront 0 holds A (and ends with the
@@ -516,7 +534,12 @@ __global__ __launch_bounds__(128) void k_evd_split(EvdArgs e) {
     block_sync();
     block_sync();
     lam = sh.lam[lane];
-    if (e.mode == 0) transform_update<KP>(e, sh, seg, jj, pl, valid, lam);
+    if (e.mode == 0) {
+      if (e.prec == 0)
+        transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam);
+      else
+        transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam);
+    }
   }
 }
 

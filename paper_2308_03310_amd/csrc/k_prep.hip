@@ -152,7 +152,13 @@ __global__ __launch_bounds__(256) void k_obs_operator(ObsArgs a) {
     val = kd == 0 ? rho : (kd == 1 ? ju / rho : jv / rho);
   }
   const double ybar = group_sum<64>(val) / (double)a.k;
-  if (m < a.kq) a.Yb[(size_t)s * a.kq + m] = m < a.k ? val - ybar : 0.0;
+  if (m < a.kq) {
+    const double dy = m < a.k ? val - ybar : 0.0;   // rounded only after the FP64 subtraction
+    if (a.Yb) a.Yb[(size_t)s * a.kq + m] = dy;
+    if (a.prec == 1) reinterpret_cast<float*>(a.Ylp)[(size_t)s * a.kq + m] = (float)dy;
+    if (a.prec == 2)
+      reinterpret_cast<unsigned short*>(a.Ylp)[(size_t)s * a.kq + m] = to_bf16((float)dy);
+  }
   if (m == 0) {
     const double var = a.var[j];
     a.d[s] = a.val[j] - ybar;

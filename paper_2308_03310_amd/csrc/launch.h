@@ -25,7 +25,9 @@ struct ObsArgs {
   int* perm;        // [n_obs]   sorted slot -> observation index
   int* ox;          // [n_obs]   sorted slot -> lattice x
   int* oy;
-  double* Yb;       // [n_obs][kq] forecast-observation perturbations (zero padded to KP)
+  double* Yb;       // [n_obs][kq] FP64 forecast-observation perturbations (zero padded to KP)
+  void* Ylp;        // the same rounded to FP32 (prec 1) or BF16 (prec 2), or null
+  int prec;
   double* d;        // [n_obs] yo - ybar
   double* rinv;     // [n_obs] 1/sigma^2 (0 for an ignored observation)
   const double* xt; // point-major ensemble [npts][9][k]
@@ -47,6 +49,7 @@ struct GramArgs {
   const int* ox;
   const int* oy;
   const double* Yb;
+  const void* Ylp;    // reduced-precision perturbations (k_gram_lp)
   const double* d;
   const double* rinv;
   double* C;          // [npt][NB][256] upper 16x16 blocks of C
@@ -58,6 +61,7 @@ struct GramArgs {
 // point-major ensemble (mode 0), or a standalone batched eigensolve (mode 1).
 struct EvdArgs {
   int mode;
+  int prec;           // contractions of the transform: 0 FP64, 1 FP32, 2 BF16 (FP32 accumulation)
   int k, npts;
   int pt0, npt;       // mode 0: points [pt0, pt0 + npt); mode 1: npt matrices
   double alpha;       // (k - 1) / rho
@@ -83,6 +87,7 @@ hipError_t launch_transpose_out(const double* xt, double* xa, int k, int npts,
                                 const int* abort_flag, hipStream_t s);
 hipError_t launch_obs_operator(const ObsArgs& a, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int kp, hipStream_t s);
+hipError_t launch_gram_lp(const GramArgs& a, int kp, int prec, hipStream_t s);
 template <int KP>
 hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s);
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
