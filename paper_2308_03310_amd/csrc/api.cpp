@@ -1,5 +1,12 @@
 // C-ABI of the LETKF library (include/letkf.h): plans, argument checks,
-// workspace ownership and the stream-ordered launch sequence of one analysis.
+// workspace ownership and the stream-ordered launch sequence of analyses.
+//
+// Per analysis (Sec. II-B, Algorithm 1): observation checks + cell binning,
+// member-major -> point-major transpose, forecast observations, then the
+// localized Gram and the eigensolve/transform/update over slabs of points,
+// then the transpose back.  A call that covers every problem of the plan once
+// runs the Gram and eigensolve kernels once per slab over the concatenated
+// points of all problems of the same eigensolver width and precision.
 #include "../../include/letkf.h"
 
 #include <hip/hip_runtime.h>
@@ -21,13 +28,13 @@ namespace {
 
 constexpr int kCell = 8;                       // observation-cell edge (lattice points)
 constexpr int kMaxDim = 32768;                 // keeps squared distances inside int32
-constexpr uint64_t kChunkBytes = 1ull << 30;   // per-chunk Gram output
+constexpr uint64_t kChunkBytes = 1ull << 30;   // Gram output (C, b) per slab
 constexpr double kJacobiTol2 = 1e-24;          // (1e-12)^2 relative off-diagonal norm
 constexpr int kJacobiMaxSweeps = 60;
 
 struct ProblemWs {
   letkf_problem p;
-  int npts, kp, nb, ncx, ncy, ncells, chunk, nobs_alloc;
+  int npts, kp, nb, ncx, ncy, ncells, nobs_alloc;
   double* xt;
   int* obs_cell;
   int* perm;
@@ -40,15 +47,26 @@ struct ProblemWs {
   void* Ylp;     // FP32 / BF16 perturbations (reduced forms)
   double* d;
   double* rinv;
-  double* C;
-  double* b;
   double* bgk;   // lattice-BGK ping-pong buffer (plans made with LETKF_FLAG_CYCLE)
+  int* abort_flag;
+};
+
+// Problems sharing an eigensolver width and precision: the Gram and
+// eigensolve kernels of a batched call run over their concatenated points.
+struct ProblemClass {
+  int kp = 16, prec = 0, nb = 1, slab = 256;
+  std::vector<int> members;   // problem indices, in order
+  GramArgs* g = nullptr;      // device [members]
+  EvdArgs* e = nullptr;       // device [members]
+  int* prefix = nullptr;      // device [members + 1]
+  int total = 0;              // points over all members
 };
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int check_problem(const letkf_problem& p) {
   if (p.nx < 1 || p.ny < 1 || p.nx > kMaxDim || p.ny > kMaxDim) return LETKF_EINVAL;
+  if ((int64_t)p.nx * p.ny > ((int64_t)1 << 30)) return LETKF_EINVAL;
   if (p.k < 2 || p.k > LETKF_MAX_K) return LETKF_EINVAL;
   if (p.n_obs_max < 0) return LETKF_EINVAL;
   if (!finite_pos(p.loc_len) || !finite_pos(p.infl)) return LETKF_EINVAL;
@@ -84,22 +102,37 @@ struct DeviceGuard {
   }
 };
 
+// Points per Gram/eigensolve launch so that the slab's C and b stay within
+// kChunkBytes (at least 256 points, at most `total`).
+int slab_points(int nb, int kp, int total) {
+  const uint64_t per_pt = ((uint64_t)nb * 256 + kp) * sizeof(double);
+  uint64_t ch = kChunkBytes / per_pt;
+  if (ch < 256) ch = 256;
+  return (int)(ch < (uint64_t)total ? ch : (uint64_t)total);
+}
+
 }  // namespace
 
 struct letkf_plan_s {
   int device = 0;
   std::vector<ProblemWs> probs;
-  int* stat = nullptr;  // device: [0] abort flag of the running call, [1] sticky status bits
+  std::vector<ProblemClass> classes;
+  GramArgs* g_one = nullptr;        // device [nprob]: descriptor of each problem
+  EvdArgs* e_one = nullptr;         // device [nprob]
+  int* prefix_one = nullptr;        // device [2 * nprob]: {0, npts} per problem
+  double* slab_C = nullptr;         // Gram output of one slab (shared by all slabs)
+  double* slab_b = nullptr;
+  int* stat = nullptr;              // device: [1] sticky status bits, [2 + p] abort flag of problem p
   std::vector<void*> allocs;
   uint64_t bytes = 0;
   std::atomic<int> busy{0};
   hipStream_t last_stream = nullptr;
-  // Phase timing: a ring of event sets, one set per timed analyze call.
+  // Phase timing: a ring of event sets, one set per timed call.
   static constexpr int kSlots = 256;
   bool timing = false;
   int nev = 0;                      // events per slot
   std::vector<hipEvent_t> ev;       // kSlots * nev
-  std::vector<int> slot_chunks;     // chunks launched in the slot's call
+  std::vector<int> slot_slabs;      // slabs launched in the slot's call
   int next_slot = 0, recorded = 0;
 
   template <class T>
@@ -130,50 +163,75 @@ void plan_sizes(ProblemWs& w) {
   w.ncx = ceil_div(p.nx, kCell);
   w.ncy = ceil_div(p.ny, kCell);
   w.ncells = w.ncx * w.ncy;
-  const uint64_t per_pt = (uint64_t)w.nb * 256 * sizeof(double);
-  uint64_t ch = kChunkBytes / per_pt;
-  if (ch < 256) ch = 256;
-  w.chunk = (int)(ch < (uint64_t)w.npts ? ch : (uint64_t)w.npts);
   w.nobs_alloc = p.n_obs_max > 0 ? p.n_obs_max : 1;
 }
 
-uint64_t ws_bytes(const ProblemWs& w) {
+uint64_t ws_bytes(const ProblemWs& w, bool cycle) {
   const uint64_t no = (uint64_t)w.nobs_alloc;
-  uint64_t b = (uint64_t)w.npts * 9 * w.p.k * sizeof(double);
-  const uint64_t ybytes = w.p.precision == LETKF_PREC_FP64 ? 8 : (w.p.precision == LETKF_PREC_FP32 ? 4 : 2);
-  b += no * 5 * sizeof(int) + no * w.kp * ybytes + no * 2 * sizeof(double);
+  const uint64_t ystride =
+      w.p.precision == LETKF_PREC_FP64 ? 8 : (w.p.precision == LETKF_PREC_FP32 ? 4 : 2);
+  const uint64_t state = (uint64_t)w.npts * 9 * w.p.k * sizeof(double);
+  uint64_t b = state * (cycle ? 2 : 1);
+  b += no * 5 * sizeof(int) + no * w.kp * ystride + no * 2 * sizeof(double);
   b += (uint64_t)(3 * w.ncells + 1) * sizeof(int);
-  b += (uint64_t)w.chunk * (w.nb * 256 + w.kp) * sizeof(double);
   return b;
 }
 
-// src: member-major background to analyse (io.xb unless a cycle left it in
-// the ping-pong buffer).
-int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool timed,
-                     const double* src) {
-  ProblemWs& w = pl->probs[io.problem];
+GramArgs gram_desc(const ProblemWs& w) {
   const letkf_problem& p = w.p;
-  const int k = p.k;
-  int* abort_flag = pl->stat;
-  hipEvent_t* ev = nullptr;
-  if (timed) {
-    const int slot = pl->next_slot;
-    pl->next_slot = (pl->next_slot + 1) % letkf_plan_s::kSlots;
-    if (pl->recorded < letkf_plan_s::kSlots) ++pl->recorded;
-    ev = &pl->ev[(size_t)slot * pl->nev];
-    pl->slot_chunks[slot] = ceil_div(w.npts, w.chunk);
+  GramArgs ga{};
+  ga.nx = p.nx;
+  ga.ny = p.ny;
+  ga.k = p.k;
+  ga.cb = kCell;
+  ga.ncx = w.ncx;
+  ga.ncy = w.ncy;
+  ga.loc = p.loc;
+  const double L = p.loc_len;
+  if (p.loc == LETKF_LOC_NONE) {
+    ga.R = -1;
+    ga.cut2 = std::numeric_limits<double>::infinity();
+  } else {
+    const double r = std::floor(2.0 * L);
+    ga.R = r >= (double)(p.nx > p.ny ? p.nx : p.ny) ? -1 : (int)r;
+    ga.cut2 = 4.0 * L * L;
   }
-  auto mark = [&](int i) {
-    if (ev) (void)hipEventRecord(ev[i], s);
-  };
-  hipError_t e;
-  mark(0);
-  if ((e = launch_fill_i32(abort_flag, 1, 0, s)) != hipSuccess) return LETKF_EDEVICE;
+  ga.inv2L2 = 1.0 / (2.0 * L * L);
+  ga.invL = 1.0 / L;
+  ga.cell_start = w.cell_start;
+  ga.ox = w.ox;
+  ga.oy = w.oy;
+  ga.Yb = w.Yb;
+  ga.Ylp = w.Ylp;
+  ga.d = w.d;
+  ga.rinv = w.rinv;
+  ga.abort_flag = w.abort_flag;
+  return ga;
+}
 
+EvdArgs evd_desc(const ProblemWs& w, int* status) {
+  const letkf_problem& p = w.p;
+  EvdArgs ea{};
+  ea.mode = 0;
+  ea.prec = p.precision;
+  ea.k = p.k;
+  ea.npts = w.npts;
+  ea.alpha = (double)(p.k - 1) / p.infl;
+  ea.sqrt_km1 = std::sqrt((double)(p.k - 1));
+  ea.tol2 = kJacobiTol2;
+  ea.max_sweeps = kJacobiMaxSweeps;
+  ea.xt = w.xt;
+  ea.abort_flag = w.abort_flag;
+  ea.status = status;
+  return ea;
+}
+
+ObsArgs obs_args(const ProblemWs& w, const letkf_io& io, int* status) {
+  const letkf_problem& p = w.p;
   ObsArgs oa{};
   oa.nx = p.nx;
   oa.ny = p.ny;
-  oa.k = k;
+  oa.k = p.k;
   oa.kq = w.kp;
   oa.npts = w.npts;
   oa.n_obs = io.n_obs;
@@ -199,82 +257,62 @@ int enqueue_analysis(letkf_plan_s* pl, const letkf_io& io, hipStream_t s, bool t
   oa.d = w.d;
   oa.rinv = w.rinv;
   oa.xt = w.xt;
-  oa.abort_flag = abort_flag;
-  oa.status = pl->stat + 1;
+  oa.abort_flag = w.abort_flag;
+  oa.status = status;
+  return oa;
+}
 
-  if (launch_bin(oa, s) != hipSuccess) return LETKF_EDEVICE;
-  mark(1);
-  if (launch_transpose_in(src, w.xt, k, w.npts, abort_flag, s) != hipSuccess) return LETKF_EDEVICE;
-  mark(2);
-  if (launch_obs_operator(oa, s) != hipSuccess) return LETKF_EDEVICE;
-  mark(3);
+hipError_t launch_gram(const BatchMap& bm, int kp, int prec, hipStream_t s) {
+  return prec == LETKF_PREC_FP64 ? launch_gram_f64(bm, kp, s) : launch_gram_lp(bm, kp, prec, s);
+}
 
-  GramArgs ga{};
-  ga.nx = p.nx;
-  ga.ny = p.ny;
-  ga.k = k;
-  ga.cb = kCell;
-  ga.ncx = w.ncx;
-  ga.ncy = w.ncy;
-  ga.loc = p.loc;
-  const double L = p.loc_len;
-  if (p.loc == LETKF_LOC_NONE) {
-    ga.R = -1;
-    ga.cut2 = std::numeric_limits<double>::infinity();
-  } else {
-    const double r = std::floor(2.0 * L);
-    ga.R = r >= (double)(p.nx > p.ny ? p.nx : p.ny) ? -1 : (int)r;
-    ga.cut2 = 4.0 * L * L;
+hipError_t launch_evd(const BatchMap& bm, int kp, hipStream_t s) {
+  if (kp == 16) return launch_evd_kp<16>(bm, s);
+  if (kp == 32) return launch_evd_kp<32>(bm, s);
+  if (kp == 64) return launch_evd_kp<64>(bm, s);
+  return hipErrorInvalidValue;
+}
+
+// Timing marks of one call: [0] start, [1] after binning, [2] after the
+// transposes, [3] after the forecast observations, then (Gram, eigensolve)
+// per slab, then the end.
+struct Marks {
+  hipEvent_t* ev = nullptr;
+  int next = 4;
+  void at(int i, hipStream_t s) const {
+    if (ev) (void)hipEventRecord(ev[i], s);
   }
-  ga.inv2L2 = 1.0 / (2.0 * L * L);
-  ga.invL = 1.0 / L;
-  ga.cell_start = w.cell_start;
-  ga.ox = w.ox;
-  ga.oy = w.oy;
-  ga.Yb = w.Yb;
-  ga.Ylp = w.Ylp;
-  ga.d = w.d;
-  ga.rinv = w.rinv;
-  ga.C = w.C;
-  ga.b = w.b;
-  ga.abort_flag = abort_flag;
+};
 
-  EvdArgs ea{};
-  ea.mode = 0;
-  ea.prec = p.precision;
-  ea.k = k;
-  ea.npts = w.npts;
-  ea.alpha = (double)(k - 1) / p.infl;
-  ea.sqrt_km1 = std::sqrt((double)(k - 1));
-  ea.tol2 = kJacobiTol2;
-  ea.max_sweeps = kJacobiMaxSweeps;
-  ea.C = w.C;
-  ea.b = w.b;
-  ea.xt = w.xt;
-  ea.abort_flag = abort_flag;
-  ea.status = pl->stat + 1;
+Marks begin_timed(letkf_plan_s* pl, int nslabs) {
+  Marks m;
+  if (!pl->timing) return m;
+  const int slot = pl->next_slot;
+  pl->next_slot = (pl->next_slot + 1) % letkf_plan_s::kSlots;
+  if (pl->recorded < letkf_plan_s::kSlots) ++pl->recorded;
+  m.ev = &pl->ev[(size_t)slot * pl->nev];
+  pl->slot_slabs[slot] = nslabs;
+  return m;
+}
 
-  int ci = 0;
-  for (int pt0 = 0; pt0 < w.npts; pt0 += w.chunk, ++ci) {
-    const int n = (w.npts - pt0) < w.chunk ? (w.npts - pt0) : w.chunk;
-    ga.pt0 = pt0;
-    ga.npt = n;
-    const hipError_t ge = p.precision == LETKF_PREC_FP64 ? launch_gram_f64(ga, w.kp, s)
-                                                         : launch_gram_lp(ga, w.kp, p.precision, s);
-    if (ge != hipSuccess) return LETKF_EDEVICE;
-    mark(4 + 2 * ci);
-    ea.pt0 = pt0;
-    ea.npt = n;
-    hipError_t le = hipErrorInvalidValue;
-    if (w.kp == 16) le = launch_evd_kp<16>(ea, s);
-    else if (w.kp == 32) le = launch_evd_kp<32>(ea, s);
-    else if (w.kp == 64) le = launch_evd_kp<64>(ea, s);
-    if (le != hipSuccess) return LETKF_EDEVICE;
-    mark(5 + 2 * ci);
+// Gram + eigensolve over the slabs of a problem table (a class or one problem).
+int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* prefix, int nprob,
+              int total, int kp, int prec, int slab, hipStream_t s, Marks& mk) {
+  BatchMap bm{};
+  bm.g = g;
+  bm.e = e;
+  bm.prefix = prefix;
+  bm.nprob = nprob;
+  bm.C = pl->slab_C;
+  bm.b = pl->slab_b;
+  for (int g0 = 0; g0 < total; g0 += slab) {
+    bm.g0 = g0;
+    bm.n = std::min(slab, total - g0);
+    if (launch_gram(bm, kp, prec, s) != hipSuccess) return LETKF_EDEVICE;
+    mk.at(mk.next++, s);
+    if (launch_evd(bm, kp, s) != hipSuccess) return LETKF_EDEVICE;
+    mk.at(mk.next++, s);
   }
-  if (launch_transpose_out(w.xt, io.xa, k, w.npts, abort_flag, s) != hipSuccess)
-    return LETKF_EDEVICE;
-  mark(4 + 2 * ci);
   return LETKF_OK;
 }
 
@@ -287,6 +325,94 @@ int check_io(const letkf_plan_s* pl, const letkf_io& io) {
       (!io.obs_ix || !io.obs_iy || !io.obs_kind || !io.obs_val || !io.obs_var))
     return LETKF_EINVAL;
   return LETKF_OK;
+}
+
+int single_slab(const ProblemWs& w) { return slab_points(w.nb, w.kp, w.npts); }
+
+// Analyses of n_io problems; src[i] is the member-major background of io[i]
+// (io[i].xb, or the cycle's ping-pong buffer).  batched: every problem of the
+// plan appears exactly once.
+int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int n_io, bool batched,
+            hipStream_t s) {
+  int* status = pl->stat + 1;
+  auto prep_bin = [&](int i) -> int {
+    const ProblemWs& w = pl->probs[io[i].problem];
+    if (launch_fill_i32(w.abort_flag, 1, 0, s) != hipSuccess) return LETKF_EDEVICE;
+    const ObsArgs oa = obs_args(w, io[i], status);
+    return launch_bin(oa, s) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+  };
+  auto prep_transpose = [&](int i) -> int {
+    const ProblemWs& w = pl->probs[io[i].problem];
+    return launch_transpose_in(src[i], w.xt, w.p.k, w.npts, w.abort_flag, s) == hipSuccess
+               ? LETKF_OK
+               : LETKF_EDEVICE;
+  };
+  auto prep_obs = [&](int i) -> int {
+    const ProblemWs& w = pl->probs[io[i].problem];
+    const ObsArgs oa = obs_args(w, io[i], status);
+    return launch_obs_operator(oa, s) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+  };
+  auto untranspose = [&](int i) -> int {
+    const ProblemWs& w = pl->probs[io[i].problem];
+    return launch_transpose_out(w.xt, io[i].xa, w.p.k, w.npts, w.abort_flag, s) == hipSuccess
+               ? LETKF_OK
+               : LETKF_EDEVICE;
+  };
+  int rc = LETKF_OK;
+  if (batched) {
+    int nslabs = 0;
+    for (const ProblemClass& c : pl->classes) nslabs += ceil_div(c.total, c.slab);
+    Marks mk = begin_timed(pl, nslabs);
+    mk.at(0, s);
+    for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_bin(i);
+    mk.at(1, s);
+    for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_transpose(i);
+    mk.at(2, s);
+    for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_obs(i);
+    mk.at(3, s);
+    for (const ProblemClass& c : pl->classes) {
+      if (rc != LETKF_OK) break;
+      rc = run_slabs(pl, c.g, c.e, c.prefix, (int)c.members.size(), c.total, c.kp, c.prec, c.slab,
+                     s, mk);
+    }
+    for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = untranspose(i);
+    mk.at(mk.next, s);
+    return rc;
+  }
+  for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
+    const int p = io[i].problem;
+    const ProblemWs& w = pl->probs[p];
+    Marks mk = i == 0 ? begin_timed(pl, ceil_div(w.npts, single_slab(w))) : Marks{};
+    mk.at(0, s);
+    rc = prep_bin(i);
+    mk.at(1, s);
+    if (rc == LETKF_OK) rc = prep_transpose(i);
+    mk.at(2, s);
+    if (rc == LETKF_OK) rc = prep_obs(i);
+    mk.at(3, s);
+    if (rc == LETKF_OK)
+      rc = run_slabs(pl, pl->g_one + p, pl->e_one + p, pl->prefix_one + 2 * p, 1, w.npts, w.kp,
+                     w.p.precision, single_slab(w), s, mk);
+    if (rc == LETKF_OK) rc = untranspose(i);
+    mk.at(mk.next, s);
+  }
+  return rc;
+}
+
+bool covers_all_once(const letkf_plan_s* pl, const letkf_io* io, int n_io) {
+  const int n = (int)pl->probs.size();
+  if (n_io != n || n < 2) return false;
+  std::vector<char> seen(n, 0);
+  for (int i = 0; i < n_io; ++i) {
+    if (seen[io[i].problem]) return false;
+    seen[io[i].problem] = 1;
+  }
+  return true;
+}
+
+template <class T>
+bool upload(const std::vector<T>& h, T* d) {
+  return hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
 }
 
 }  // namespace
@@ -317,14 +443,42 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     if (rc != LETKF_OK) return rc;
   }
   std::vector<ProblemWs> ws(n_probs);
-  uint64_t total = 64;
   for (int i = 0; i < n_probs; ++i) {
     std::memset(&ws[i], 0, sizeof(ProblemWs));
     ws[i].p = probs[i];
     plan_sizes(ws[i]);
-    total += ws_bytes(ws[i]);
-    if (cycle) total += (uint64_t)ws[i].npts * 9 * probs[i].k * sizeof(double);
   }
+  // classes by (width, precision), in order of first appearance
+  std::vector<ProblemClass> classes;
+  for (int i = 0; i < n_probs; ++i) {
+    int c = 0;
+    while (c < (int)classes.size() &&
+           !(classes[c].kp == ws[i].kp && classes[c].prec == ws[i].p.precision))
+      ++c;
+    if (c == (int)classes.size()) {
+      ProblemClass pc;
+      pc.kp = ws[i].kp;
+      pc.prec = ws[i].p.precision;
+      pc.nb = ws[i].nb;
+      classes.push_back(pc);
+    }
+    classes[c].members.push_back(i);
+    classes[c].total += ws[i].npts;
+  }
+  // slab buffers: the largest slab of any class or single problem
+  uint64_t c_doubles = 0, b_doubles = 0;
+  for (auto& c : classes) {
+    c.slab = slab_points(c.nb, c.kp, c.total);
+    c_doubles = std::max(c_doubles, (uint64_t)c.slab * c.nb * 256);
+    b_doubles = std::max(b_doubles, (uint64_t)c.slab * c.kp);
+  }
+  for (auto& w : ws) {
+    const uint64_t sl = (uint64_t)single_slab(w);
+    c_doubles = std::max(c_doubles, sl * w.nb * 256);
+    b_doubles = std::max(b_doubles, sl * w.kp);
+  }
+  uint64_t total = 4096 + (c_doubles + b_doubles) * sizeof(double);
+  for (auto& w : ws) total += ws_bytes(w, cycle);
   if (opt && opt->hbm_budget_bytes && total > opt->hbm_budget_bytes) return LETKF_ENOMEM;
   int dev = 0;
   const int drc = check_device(&dev);
@@ -334,10 +488,13 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
   if (!pl) return LETKF_ENOMEM;
   pl->device = dev;
   pl->probs = ws;
-  bool ok = pl->alloc(&pl->stat, 4);
-  for (auto& w : pl->probs) {
+  pl->classes = classes;
+  bool ok = pl->alloc(&pl->stat, 2 + (size_t)n_probs);
+  for (int i = 0; ok && i < n_probs; ++i) {
+    ProblemWs& w = pl->probs[i];
     const int k = w.p.k;
     const size_t no = (size_t)w.nobs_alloc;
+    w.abort_flag = pl->stat + 2 + i;
     ok = ok && pl->alloc(&w.xt, (size_t)w.npts * 9 * k);
     ok = ok && pl->alloc(&w.obs_cell, no) && pl->alloc(&w.perm, no) && pl->alloc(&w.ox, no) &&
          pl->alloc(&w.oy, no);
@@ -351,20 +508,48 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     ok = ok && pl->alloc(&w.d, no) && pl->alloc(&w.rinv, no);
     ok = ok && pl->alloc(&w.cell_count, w.ncells) && pl->alloc(&w.cell_start, w.ncells + 1) &&
          pl->alloc(&w.cell_fill, w.ncells);
-    ok = ok && pl->alloc(&w.C, (size_t)w.chunk * w.nb * 256) && pl->alloc(&w.b, (size_t)w.chunk * w.kp);
     if (cycle) ok = ok && pl->alloc(&w.bgk, (size_t)w.npts * 9 * k);
+  }
+  ok = ok && pl->alloc(&pl->slab_C, (size_t)c_doubles) && pl->alloc(&pl->slab_b, (size_t)b_doubles);
+  // descriptors: one per problem, and one table per class
+  std::vector<GramArgs> g_host(n_probs);
+  std::vector<EvdArgs> e_host(n_probs);
+  std::vector<int> pre_host(2 * (size_t)n_probs);
+  for (int i = 0; ok && i < n_probs; ++i) {
+    g_host[i] = gram_desc(pl->probs[i]);
+    e_host[i] = evd_desc(pl->probs[i], pl->stat + 1);
+    pre_host[2 * i] = 0;
+    pre_host[2 * i + 1] = pl->probs[i].npts;
+  }
+  ok = ok && pl->alloc(&pl->g_one, n_probs) && pl->alloc(&pl->e_one, n_probs) &&
+       pl->alloc(&pl->prefix_one, 2 * (size_t)n_probs);
+  ok = ok && upload(g_host, pl->g_one) && upload(e_host, pl->e_one) &&
+       upload(pre_host, pl->prefix_one);
+  for (auto& c : pl->classes) {
     if (!ok) break;
+    const size_t n = c.members.size();
+    std::vector<GramArgs> gc(n);
+    std::vector<EvdArgs> ec(n);
+    std::vector<int> pc(n + 1, 0);
+    for (size_t j = 0; j < n; ++j) {
+      gc[j] = g_host[c.members[j]];
+      ec[j] = e_host[c.members[j]];
+      pc[j + 1] = pc[j] + pl->probs[c.members[j]].npts;
+    }
+    ok = ok && pl->alloc(&c.g, n) && pl->alloc(&c.e, n) && pl->alloc(&c.prefix, n + 1);
+    ok = ok && upload(gc, c.g) && upload(ec, c.e) && upload(pc, c.prefix);
   }
   if (ok && opt && (opt->flags & LETKF_FLAG_PHASE_TIMING)) {
-    int max_chunks = 1;
-    for (auto& w : pl->probs) max_chunks = std::max(max_chunks, ceil_div(w.npts, w.chunk));
+    int max_slabs = 0;
+    for (auto& c : pl->classes) max_slabs += ceil_div(c.total, c.slab);
+    for (auto& w : pl->probs) max_slabs = std::max(max_slabs, ceil_div(w.npts, single_slab(w)));
     pl->timing = true;
-    pl->nev = 5 + 2 * max_chunks;
+    pl->nev = 5 + 2 * max_slabs;
     pl->ev.resize((size_t)letkf_plan_s::kSlots * pl->nev);
-    pl->slot_chunks.assign(letkf_plan_s::kSlots, 0);
+    pl->slot_slabs.assign(letkf_plan_s::kSlots, 0);
     for (auto& e : pl->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
   }
-  if (!ok || hipMemset(pl->stat, 0, 4 * sizeof(int)) != hipSuccess ||
+  if (!ok || hipMemset(pl->stat, 0, (2 + (size_t)n_probs) * sizeof(int)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     pl->release();
     delete pl;
@@ -375,7 +560,7 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
 }
 
 int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream) {
-  if (!plan || !io || n_io < 0) return LETKF_EINVAL;
+  if (!plan || (!io && n_io > 0) || n_io < 0) return LETKF_EINVAL;
   for (int i = 0; i < n_io; ++i) {
     const int rc = check_io(plan, io[i]);
     if (rc != LETKF_OK) return rc;
@@ -384,16 +569,16 @@ int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip
   if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc = LETKF_OK;
-  for (int i = 0; i < n_io && rc == LETKF_OK; ++i)
-    rc = enqueue_analysis(plan, io[i], s, plan->timing && i == 0, io[i].xb);
+  std::vector<const double*> src(n_io);
+  for (int i = 0; i < n_io; ++i) src[i] = io[i].xb;
+  const int rc = enqueue(plan, io, src.data(), n_io, covers_all_once(plan, io, n_io), s);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;
 }
 
 int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream) {
-  if (!plan || !io || n_io < 0) return LETKF_EINVAL;
+  if (!plan || (!io && n_io > 0) || n_io < 0) return LETKF_EINVAL;
   for (int i = 0; i < n_io; ++i) {
     const int rc = check_io(plan, io[i].io);
     if (rc != LETKF_OK) return rc;
@@ -407,6 +592,8 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   int rc = LETKF_OK;
+  std::vector<letkf_io> ios(n_io);
+  std::vector<const double*> src(n_io);
   for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
     const letkf_cycle_io& c = io[i];
     ProblemWs& w = plan->probs[c.io.problem];
@@ -417,12 +604,13 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
       if (launch_bgk(cur, nxt, w.p.k, w.p.nx, w.p.ny, c.tau, c.force_amp, c.force_kx, s) !=
           hipSuccess)
         rc = LETKF_EDEVICE;
-      double* t = cur;
-      cur = nxt;
-      nxt = t;
+      std::swap(cur, nxt);
     }
-    if (rc == LETKF_OK) rc = enqueue_analysis(plan, c.io, s, plan->timing && i == 0, cur);
+    ios[i] = c.io;
+    src[i] = cur;
   }
+  if (rc == LETKF_OK)
+    rc = enqueue(plan, ios.data(), src.data(), n_io, covers_all_once(plan, ios.data(), n_io), s);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;
@@ -461,13 +649,13 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
   DeviceGuard guard(plan->device);
   if (hipStreamSynchronize(plan->last_stream) != hipSuccess) return -LETKF_EDEVICE;
   double acc[LETKF_N_PHASES] = {0, 0, 0, 0, 0, 0};
-  int last_chunks = 0;
+  int last_slabs = 0;
   const int calls = plan->recorded;
   for (int c = 0; c < calls; ++c) {
     const int slot = (plan->next_slot - 1 - c + 2 * letkf_plan_s::kSlots) % letkf_plan_s::kSlots;
     const hipEvent_t* ev = &plan->ev[(size_t)slot * plan->nev];
-    const int nch = plan->slot_chunks[slot];
-    last_chunks = nch;
+    const int nsl = plan->slot_slabs[slot];
+    last_slabs = nsl;
     float t = 0.f;
     auto el = [&](int a, int b) -> double {
       return hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess ? (double)t : 0.0;
@@ -476,15 +664,15 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
     acc[LETKF_PHASE_TRANSPOSE] += el(1, 2);
     acc[LETKF_PHASE_OBSOP] += el(2, 3);
     int prev = 3;
-    for (int ci = 0; ci < nch; ++ci) {
+    for (int ci = 0; ci < nsl; ++ci) {
       acc[LETKF_PHASE_GRAM] += el(prev, 4 + 2 * ci);
       acc[LETKF_PHASE_EVD] += el(4 + 2 * ci, 5 + 2 * ci);
       prev = 5 + 2 * ci;
     }
-    acc[LETKF_PHASE_UNTRANS] += el(prev, 4 + 2 * nch);
+    acc[LETKF_PHASE_UNTRANS] += el(prev, 4 + 2 * nsl);
   }
-  const int bin_launches = 5;  // two fills, count, scan, scatter/sort share the phase
-  const int per_call[LETKF_N_PHASES] = {bin_launches, 1, 1, last_chunks, last_chunks, 1};
+  const int bin_launches = 5;  // two fills, count, scan, scatter + sort
+  const int per_call[LETKF_N_PHASES] = {bin_launches, 1, 1, last_slabs, last_slabs, 1};
   for (int i = 0; i < n; ++i) {
     ms[i] = i < LETKF_N_PHASES ? acc[i] : 0.0;
     if (launches) launches[i] = i < LETKF_N_PHASES ? per_call[i] : 0;
@@ -498,23 +686,23 @@ int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, d
   if (batch < 0 || k < 1 || k > LETKF_MAX_K) return LETKF_EINVAL;
   if (batch == 0) return LETKF_OK;
   if (!a || !lam || !vec) return LETKF_EINVAL;
-  EvdArgs ea{};
+  BatchMap bm{};
+  bm.nprob = 1;
+  bm.g0 = 0;
+  bm.n = batch;
+  EvdArgs& ea = bm.e_inline;
   ea.mode = 1;
   ea.k = k;
-  ea.npt = batch;
+  ea.npts = batch;
   ea.tol2 = kJacobiTol2;
   ea.max_sweeps = kJacobiMaxSweeps;
   ea.A = a;
   ea.lam = lam;
   ea.vec = vec;
   ea.status = status;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int kp = pow2_at_least16(k);
-  hipError_t e = hipErrorInvalidValue;
-  if (kp == 16) e = launch_evd_kp<16>(ea, s);
-  else if (kp == 32) e = launch_evd_kp<32>(ea, s);
-  else if (kp == 64) e = launch_evd_kp<64>(ea, s);
-  return e == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+  return launch_evd(bm, kp, static_cast<hipStream_t>(hip_stream)) == hipSuccess ? LETKF_OK
+                                                                                 : LETKF_EDEVICE;
 }
 
 }  // extern "C"

@@ -445,15 +445,30 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
 }
 
 // One wavefront holds both A and V rows of 64/KP matrices (KP = 16, 32).
+// The descriptor of the problem that owns slab-local point pl, with C and b
+// pointed at the slab and pt0 set so that pt0 + pl is the point within its
+// problem (every helper indexes C, b by pl and the ensemble by pt0 + pl).
+__device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool& valid) {
+  valid = pl < bm.n;
+  const int gidx = bm.g0 + (valid ? pl : 0);
+  const int prob = bm.prefix ? find_problem(bm.prefix, bm.nprob, gidx) : 0;
+  EvdArgs e = bm.e ? bm.e[prob] : bm.e_inline;
+  e.C = bm.C;
+  e.b = bm.b;
+  e.pt0 = gidx - (bm.prefix ? bm.prefix[prob] : 0) - (valid ? pl : 0);
+  if (e.abort_flag && *e.abort_flag) valid = false;
+  return e;
+}
+
 template <int KP>
-__global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
+__global__ __launch_bounds__(64) void k_evd(BatchMap bm) {
   constexpr int G = 64 / KP;
   __shared__ EvdLds<KP> sh;
-  if (e.abort_flag && *e.abort_flag) return;
   const int lane = lane_id();
   const int seg = lane / KP, jj = lane % KP;
   const int pl = blockIdx.x * G + seg;
-  const bool valid = pl < e.npt;
+  bool valid;
+  const EvdArgs e = evd_args_of(bm, pl, valid);
   double* M = sh.mat[seg];
   stage_matrix<KP>(e, sh, seg, jj, pl, valid);
   wave_lds_sync();
@@ -481,17 +496,18 @@ __global__ __launch_bounds__(64) void k_evd(EvdArgs e) {
 // Two wavefronts per block: wavefront 0 holds A (and ends with the
 // eigenvalues), wavefront 1 holds V and does the transform.
 template <int KP>
-__global__ __launch_bounds__(128) void k_evd_split(EvdArgs e) {
+__global__ __launch_bounds__(128) void k_evd_split(BatchMap bm) {
   constexpr int G = 64 / KP;
   __shared__ EvdLds<KP> sh;
-  if (e.abort_flag && *e.abort_flag) return;
   // wave-uniform role (readfirstlane makes the branch provably uniform, so A
   // and V never share one wavefront's registers)
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
   const int seg = lane / KP, jj = lane % KP;
   const int pl = blockIdx.x * G + seg;
-  const bool valid = pl < e.npt;
+  bool valid;
+  const EvdArgs e = evd_args_of(bm, pl, valid);
+  if (!valid) return;   // G = 1: the whole block shares one point (uniform exit, before any barrier)
   double* M = sh.mat[seg];
   if (wid == 0) stage_matrix<KP>(e, sh, seg, jj, pl, valid);
   block_sync();
@@ -544,8 +560,9 @@ __global__ __launch_bounds__(128) void k_evd_split(EvdArgs e) {
 }
 
 template <int KP>
-hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s) {
-  const dim3 grid(ceil_div(a.npt, 64 / KP));
+hipError_t launch_evd_kp(const BatchMap& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  const dim3 grid(ceil_div(a.n, 64 / KP));
   if constexpr (KP == 64) {
     hipLaunchKernelGGL(k_evd_split<KP>, grid, dim3(128), 0, s, a);
   } else {

@@ -3,5 +3,5 @@
 #include "k_evd.h"
 
 namespace letkf {
-template hipError_t launch_evd_kp<16>(const EvdArgs&, hipStream_t);
+template hipError_t launch_evd_kp<16>(const BatchMap&, hipStream_t);
 }  // namespace letkf

@@ -107,18 +107,21 @@ __device__ __forceinline__ void gram_step(GramAcc<KQ>& acc, const GramArgs& g, c
 }
 
 template <int KQ>
-__global__ __launch_bounds__(256) void k_gram_f64(GramArgs g) {
+__global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   __shared__ int s_ring[4][128];
   __shared__ double w_ring[4][128];
-  if (*g.abort_flag) return;
   const int wid = threadIdx.x >> 6, lane = lane_id();
   const int nblocks = gridDim.x;
   const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int pl = lb * 4 + wid;
-  if (pl >= g.npt) return;
-  const int pt = g.pt0 + pl;
+  const int pl = lb * 4 + wid;            // slab-local point
+  if (pl >= bm.n) return;
+  const int gidx = bm.g0 + pl;
+  const int prob = find_problem(bm.prefix, bm.nprob, gidx);
+  const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
+  if (*g.abort_flag) return;
+  const int pt = gidx - bm.prefix[prob];  // point within its problem
   const int x = pt % g.nx, y = pt / g.nx;
   int* ring_s = s_ring[wid];
   double* ring_w = w_ring[wid];
@@ -187,11 +190,11 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs g) {
     double v = acc.bacc[I];
     v += xor_lane<16>(v);
     v += xor_lane<32>(v);
-    if (lane < 16) g.b[(size_t)pl * KQ + 16 * I + lane] = v;
+    if (lane < 16) bm.b[(size_t)pl * KQ + 16 * I + lane] = v;
   }
   // C blocks: the f64 16x16x4 accumulator gives lane l, element r the entry
   // (row 4*r + l/16, column l%16) of each block.
-  double* out = g.C + (size_t)pl * NB * 256;
+  double* out = bm.C + (size_t)pl * NB * 256;
   const int e = lane >> 4, col = lane & 15;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -200,8 +203,9 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs g) {
   }
 }
 
-hipError_t launch_gram_f64(const GramArgs& a, int kp, hipStream_t s) {
-  const dim3 grid(ceil_div(a.npt, 4)), block(256);
+hipError_t launch_gram_f64(const BatchMap& a, int kp, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  const dim3 grid(ceil_div(a.n, 4)), block(256);
   switch (kp) {
     case 16: hipLaunchKernelGGL(k_gram_f64<16>, grid, block, 0, s, a); break;
     case 32: hipLaunchKernelGGL(k_gram_f64<32>, grid, block, 0, s, a); break;

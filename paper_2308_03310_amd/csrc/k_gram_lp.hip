@@ -150,18 +150,21 @@ __device__ __forceinline__ void gram_step_bf16(GramAccLp<KQ, 2>& acc, const Gram
 }
 
 template <int KQ, int PREC>
-__global__ __launch_bounds__(256) void k_gram_lp(GramArgs g) {
+__global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   constexpr int STEP = PREC == 1 ? 4 : 16;
   __shared__ int s_ring[4][128];
   __shared__ double w_ring[4][128];
-  if (*g.abort_flag) return;
   const int wid = threadIdx.x >> 6, lane = lane_id();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int pl = lb * 4 + wid;
-  if (pl >= g.npt) return;
-  const int pt = g.pt0 + pl;
+  const int pl = lb * 4 + wid;            // slab-local point
+  if (pl >= bm.n) return;
+  const int gidx = bm.g0 + pl;
+  const int prob = find_problem(bm.prefix, bm.nprob, gidx);
+  const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
+  if (*g.abort_flag) return;
+  const int pt = gidx - bm.prefix[prob];
   const int x = pt % g.nx, y = pt / g.nx;
   int* ring_s = s_ring[wid];
   double* ring_w = w_ring[wid];
@@ -230,9 +233,9 @@ __global__ __launch_bounds__(256) void k_gram_lp(GramArgs g) {
     double v = (double)acc.bacc[I];
     v += xor_lane<16>(v);
     v += xor_lane<32>(v);
-    if (lane < 16) g.b[(size_t)pl * KQ + 16 * I + lane] = v;
+    if (lane < 16) bm.b[(size_t)pl * KQ + 16 * I + lane] = v;
   }
-  double* out = g.C + (size_t)pl * NB * 256;
+  double* out = bm.C + (size_t)pl * NB * 256;
   const int col = lane & 15;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -241,8 +244,9 @@ __global__ __launch_bounds__(256) void k_gram_lp(GramArgs g) {
   }
 }
 
-hipError_t launch_gram_lp(const GramArgs& a, int kp, int prec, hipStream_t s) {
-  const dim3 grid(ceil_div(a.npt, 4)), block(256);
+hipError_t launch_gram_lp(const BatchMap& a, int kp, int prec, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  const dim3 grid(ceil_div(a.n, 4)), block(256);
 #define LETKF_GRAM_LP(KP_, PR_) \
   if (kp == KP_ && prec == PR_) { hipLaunchKernelGGL((k_gram_lp<KP_, PR_>), grid, block, 0, s, a); return hipGetLastError(); }
   LETKF_GRAM_LP(16, 1)

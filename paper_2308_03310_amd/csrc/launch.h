@@ -78,6 +78,30 @@ struct EvdArgs {
   int* status;
 };
 
+// A launch of the Gram or eigensolve kernels over a slab of points taken from
+// the concatenated point lists of several problems (one problem is a table
+// of one).  Descriptors live in device memory; C and b of the slab are
+// indexed by the slab-local point.
+struct BatchMap {
+  const GramArgs* g;   // [nprob]
+  const EvdArgs* e;    // [nprob]; null: one problem described by e_inline
+  const int* prefix;   // [nprob + 1] first global point of each problem; null: {0}
+  int nprob;
+  int g0, n;           // slab: global points [g0, g0 + n)
+  double* C;           // [n][NB][256]
+  double* b;           // [n][KP]
+  EvdArgs e_inline;
+};
+
+__device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gidx) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= gidx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // --- launchers (return hipError_t of the launch) ---
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
 hipError_t launch_bin(const ObsArgs& a, hipStream_t s);
@@ -86,10 +110,10 @@ hipError_t launch_transpose_in(const double* xb, double* xt, int k, int npts, co
 hipError_t launch_transpose_out(const double* xt, double* xa, int k, int npts,
                                 const int* abort_flag, hipStream_t s);
 hipError_t launch_obs_operator(const ObsArgs& a, hipStream_t s);
-hipError_t launch_gram_f64(const GramArgs& a, int kp, hipStream_t s);
-hipError_t launch_gram_lp(const GramArgs& a, int kp, int prec, hipStream_t s);
+hipError_t launch_gram_f64(const BatchMap& bm, int kp, hipStream_t s);
+hipError_t launch_gram_lp(const BatchMap& bm, int kp, int prec, hipStream_t s);
 template <int KP>
-hipError_t launch_evd_kp(const EvdArgs& a, hipStream_t s);
+hipError_t launch_evd_kp(const BatchMap& bm, hipStream_t s);
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
                       int force_kx, hipStream_t s);
 
