@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--workload", default="grid256_k32", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests of the serving run (0 to skip)")
+    ap.add_argument("--serving-rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -200,6 +203,17 @@ def main():
         "phases_ms_per_step": {k: round(v, 4) for k, v in per_call.items()},
         "host_wall_s": round(wall, 3),
     }
+    if args.serving_requests > 0:
+        from paper_2308_03310_amd import serving
+        srv = serving.AssimilationServer(serving.default_specs(16), budget_bytes=200 << 30,
+                                         n_slots=8)
+        try:
+            srv.run_poisson(args.serving_rate, 16, seed=40)       # warm-up: admit every session
+            out["serving"] = srv.run_poisson(args.serving_rate, args.serving_requests, seed=4)
+            out["serving"]["sessions"] = len(srv.sessions)
+            out["serving"]["cycle"] = "50 BGK steps (tau 0.52, Kolmogorov forcing 1e-5) + analysis"
+        finally:
+            srv.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
