@@ -8,245 +8,39 @@
 //     W     = sqrt(k-1) V diag(lam^-1/2) V^T          eq. (letkf_dwa)
 //     X^a   = xbar 1^T + dX (wbar 1^T + W)            eq. (letkf_xa), 9 components share W
 //
-// Eigensolver: cyclic two-sided Jacobi (Golub & Van Loan, Matrix
-// Computations, Sec. 8.5 "Jacobi methods": sym.schur2 rotation, cyclic
-// sweeps).  Within a sweep the k(k-1)/2 index pairs are ordered in KP-1
-// rounds; round m pairs row p with row p XOR m, so each round is k/2
-// disjoint rotations that run in parallel, one matrix row per lane.  A KP-row
-// matrix occupies KP lanes of a wavefront (KP = 16, 32, 64), so 64/KP
-// matrices share one wavefront.  Sizes below KP are padded with decoupled
-// unit diagonal rows, which no rotation ever touches.
-//
-// Register layout ("diagonal layout"): lane j holds a[u] = A[j][j^u] and
-// v[u] = V[j][j^u] for u = 0..KP-1, so the diagonal is a[0], the pivot of
-// round m is a[m], and both the row exchange (partner row, xor-m lane
-// shuffle) and the column rotation (slots u, u^m) use compile-time register
-// indices.
+// Eigensolver (the batched EVD of Sec. III, one matrix per KP lanes of a
+// wavefront, 64/KP matrices per wavefront):
+//   1. Householder reduction to tridiagonal form T = H^T Q H (Golub & Van
+//      Loan, Matrix Computations, Sec. 8.3.1), one matrix row per lane in
+//      registers; the reflector of step i is broadcast through LDS and the
+//      symmetric rank-2 update A -= v w^T + w v^T runs in-lane.
+//   2. H = H_0 H_1 ... H_{n-3} accumulated row by row in registers, then
+//      stored to LDS (natural layout, row stride KP+1).
+//   3. Implicit QL iterations with Wilkinson's shift on T (Bowdler, Martin,
+//      Reinsch & Wilkinson 1968, "The QR and QL algorithms for symmetric
+//      matrices"), each plane rotation applied to the columns of H in LDS, so
+//      that H ends as the eigenvector matrix V.  Every lane of a matrix runs
+//      the same scalar rotation chain (the chain is uniform per matrix); the
+//      lane owns one row of V.  Deflation is tested lane-parallel (lane j
+//      tests the subdiagonal entry e_j) and resolved with a ballot.
+// Sizes below KP are padded with decoupled unit rows; their subdiagonal
+// entries are exactly zero, so no rotation ever couples them to the matrix.
 #pragma once
 #include "common.h"
 #include "launch.h"
 
 namespace letkf {
 
-template <int M>
-__host__ __device__ constexpr int high_bit() {
-  int h = 1;
-  while ((h << 1) <= M) h <<= 1;
-  return h;
-}
-
-// Slot of the R-th pair representative of mask M: R with a zero bit inserted
-// at the position of M's highest set bit (so slot < slot ^ M).
-template <int M, int R>
-__host__ __device__ constexpr int rep_slot() {
-  constexpr int HB = high_bit<M>();
-  return ((R & ~(HB - 1)) << 1) | (R & (HB - 1));
-}
-
-#ifndef LETKF_JACOBI_PAIR_GROUP
-#define LETKF_JACOBI_PAIR_GROUP 0
+// Target waves per SIMD for the register allocator of the eigensolve kernel.
+#ifndef LETKF_EVD_WAVES
+#define LETKF_EVD_WAVES 2
 #endif
 
-template <int R>
-__device__ __forceinline__ void pair_group_fence() {
-  constexpr int G = LETKF_JACOBI_PAIR_GROUP;
-  if constexpr (G > 0 && R % G == G - 1) __builtin_amdgcn_sched_barrier(0);
-}
-
-// Row exchange + column rotation of the slot pair (U, U^M) of this lane's row.
-template <int KP, int M, int U>
-__device__ __forceinline__ void jacobi_pair(double (&a)[KP], double (&v)[KP], int jj, double c,
-                                            double sr, const double2* cb) {
-  constexpr int UM = U ^ M;
-  const double pu = xor_lane<M>(a[UM]);   // partner row, column jj^U
-  const double pum = xor_lane<M>(a[U]);   // partner row, column jj^U^M
-  const double x0 = fma(sr, pu, c * a[U]);
-  const double x1 = fma(sr, pum, c * a[UM]);
-  const double2 cf = cb[jj ^ U];          // rotation of column jj^U
-  a[U] = fma(cf.y, x1, cf.x * x0);
-  a[UM] = fma(-cf.y, x0, cf.x * x1);
-  const double v0 = v[U], v1 = v[UM];
-  v[U] = fma(cf.y, v1, cf.x * v0);
-  v[UM] = fma(-cf.y, v0, cf.x * v1);
-}
-
-template <int KP, int M, int... Rs>
-__device__ __forceinline__ void jacobi_pairs(double (&a)[KP], double (&v)[KP], int jj, double c,
-                                             double sr, const double2* cb,
-                                             std::integer_sequence<int, Rs...>) {
-  ((jacobi_pair<KP, M, rep_slot<M, Rs>()>(a, v, jj, c, sr, cb), pair_group_fence<Rs>()), ...);
-}
-
-// One round: rotations (j, j^M) for every lane j.  cb is this matrix's
-// coefficient buffer in LDS (KP entries of (c, signed s)).
-template <int KP, int M>
-__device__ __forceinline__ void jacobi_round(double (&a)[KP], double (&v)[KP], int jj, double2* cb) {
-  constexpr int HB = high_bit<M>();
-  const bool lo = (jj & HB) == 0;  // this lane is p (the smaller index) of its pair
-  const double d_self = a[0];
-  const double d_oth = xor_lane<M>(d_self);
-  const double o_self = a[M];
-  const double o_oth = xor_lane<M>(o_self);
-  // Both lanes of a pair use the p-lane's copies, so they agree bitwise.
-  const double app = lo ? d_self : d_oth;
-  const double aqq = lo ? d_oth : d_self;
-  const double apq = lo ? o_self : o_oth;
-  // Branch-free sym.schur2: t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)) is the
-  // smaller root of t^2 + 2 zeta t - 1 = 0; apq = 0 gives the identity.  When
-  // zeta^2 overflows, t rounds to 0 and the (negligible) pivot is dropped.
-  const bool nz = apq != 0.0;
-  const double zeta = (aqq - app) / (2.0 * (nz ? apq : 1.0));
-  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-  const double t = nz ? tt : 0.0;
-  const double c = rsqrt(fma(t, t, 1.0));
-  const double s = t * c;
-  // J restricted to (p,q) is [[c, s], [-s, c]]; row j of J^T A is
-  // c*A[j,:] + sr*A[j^M,:] with sr = -s on p and +s on q, and the same
-  // (c, sr) of lane l rotates column l.
-  const double sr = lo ? -s : s;
-  cb[jj] = make_double2(c, sr);
-  wave_lds_sync();
-  // Opaque copy of the lane index: keeps the per-slot LDS addresses jj^U
-  // from being hoisted out of the sweep loop (they would stay live in VGPRs).
-  int jr;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(jr) : "v"(jj));
-  jacobi_pairs<KP, M>(a, v, jr, c, sr, cb, std::make_integer_sequence<int, KP / 2>{});
-  a[0] = lo ? fma(-t, apq, app) : fma(t, apq, aqq);
-  a[M] = 0.0;
-}
-
-template <int KP, int... Ms>
-__device__ __forceinline__ void jacobi_sweep_impl(double (&a)[KP], double (&v)[KP], int jj,
-                                                  double2* cb0, double2* cb1,
-                                                  std::integer_sequence<int, Ms...>) {
-  (jacobi_round<KP, Ms + 1>(a, v, jj, (Ms & 1) ? cb1 : cb0), ...);
-}
-
-template <int KP>
-__device__ __forceinline__ void jacobi_sweep(double (&a)[KP], double (&v)[KP], int jj,
-                                             double2* cb0, double2* cb1) {
-  jacobi_sweep_impl<KP>(a, v, jj, cb0, cb1, std::make_integer_sequence<int, KP - 1>{});
-}
-
-// Runs sweeps until every matrix of the wavefront has a relative squared
-// off-diagonal Frobenius norm <= tol2; returns false if max_sweeps ran out.
-template <int KP>
-__device__ __forceinline__ bool jacobi_solve(double (&a)[KP], double (&v)[KP], int jj,
-                                             double2* cb0, double2* cb1, double tol2,
-                                             int max_sweeps) {
-  for (int sweep = 0;; ++sweep) {
-    double off = 0.0;
-#pragma unroll
-    for (int u = 1; u < KP; ++u) off = fma(a[u], a[u], off);
-    const double dg = a[0] * a[0];
-    const double off_s = group_sum<KP>(off), dg_s = group_sum<KP>(dg);
-    const bool conv = off_s <= tol2 * dg_s;
-    if (__ballot(!conv) == 0) return true;
-    if (sweep >= max_sweeps) return false;
-    jacobi_sweep<KP>(a, v, jj, cb0, cb1);
-  }
-}
-
-// ---- split solve: wavefront 0 holds A and computes the rotations, wavefront
-// 1 holds V and applies them; one workgroup barrier per round publishes the
-// coefficient buffer.  Used for 64-row matrices, whose A and V rows (2 x 128
-// VGPRs) do not fit one wavefront's registers.
-__device__ __forceinline__ void block_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ int opaque_lane(int jj) {
-  int jr;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(jr) : "v"(jj));
-  return jr;
-}
-
-template <int KP, int M, int U>
-__device__ __forceinline__ void jacobi_pair_a(double (&a)[KP], int jj, double c, double sr,
-                                              const double2* cb) {
-  constexpr int UM = U ^ M;
-  const double pu = xor_lane<M>(a[UM]);
-  const double pum = xor_lane<M>(a[U]);
-  const double x0 = fma(sr, pu, c * a[U]);
-  const double x1 = fma(sr, pum, c * a[UM]);
-  const double2 cf = cb[jj ^ U];
-  a[U] = fma(cf.y, x1, cf.x * x0);
-  a[UM] = fma(-cf.y, x0, cf.x * x1);
-}
-
-template <int R>
-__device__ __forceinline__ void v_pair_fence() {
-  if constexpr (R % 8 == 7) __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int KP, int M, int U>
-__device__ __forceinline__ void jacobi_pair_v(double (&v)[KP], int jj, const double2* cb) {
-  constexpr int UM = U ^ M;
-  const double2 cf = cb[jj ^ U];
-  const double v0 = v[U], v1 = v[UM];
-  v[U] = fma(cf.y, v1, cf.x * v0);
-  v[UM] = fma(-cf.y, v0, cf.x * v1);
-}
-
-template <int KP, int M, int... Rs>
-__device__ __forceinline__ void jacobi_round_a(double (&a)[KP], int jj, double2* cb,
-                                               std::integer_sequence<int, Rs...>) {
-  constexpr int HB = high_bit<M>();
-  const bool lo = (jj & HB) == 0;
-  const double d_self = a[0];
-  const double d_oth = xor_lane<M>(d_self);
-  const double o_self = a[M];
-  const double o_oth = xor_lane<M>(o_self);
-  const double app = lo ? d_self : d_oth;
-  const double aqq = lo ? d_oth : d_self;
-  const double apq = lo ? o_self : o_oth;
-  const bool nz = apq != 0.0;
-  const double zeta = (aqq - app) / (2.0 * (nz ? apq : 1.0));
-  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-  const double t = nz ? tt : 0.0;
-  const double c = rsqrt(fma(t, t, 1.0));
-  const double s = t * c;
-  const double sr = lo ? -s : s;
-  cb[jj] = make_double2(c, sr);
-  block_sync();
-  const int jr = opaque_lane(jj);
-  (jacobi_pair_a<KP, M, rep_slot<M, Rs>()>(a, jr, c, sr, cb), ...);
-  a[0] = lo ? fma(-t, apq, app) : fma(t, apq, aqq);
-  a[M] = 0.0;
-}
-
-template <int KP, int M, int... Rs>
-__device__ __forceinline__ void jacobi_round_v(double (&v)[KP], int jj, const double2* cb,
-                                               std::integer_sequence<int, Rs...>) {
-  block_sync();
-  const int jr = opaque_lane(jj);
-  // fences every 8 pairs: otherwise all KP/2 coefficient loads of the round
-  // are hoisted and live next to V's own 2*KP registers
-  ((jacobi_pair_v<KP, M, rep_slot<M, Rs>()>(v, jr, cb), v_pair_fence<Rs>()), ...);
-}
-
-template <int KP, int... Ms>
-__device__ __forceinline__ void jacobi_sweep_a(double (&a)[KP], int jj, double2* cb0, double2* cb1,
-                                               std::integer_sequence<int, Ms...>) {
-  (jacobi_round_a<KP, Ms + 1>(a, jj, (Ms & 1) ? cb1 : cb0,
-                              std::make_integer_sequence<int, KP / 2>{}), ...);
-}
-
-template <int KP, int... Ms>
-__device__ __forceinline__ void jacobi_sweep_v(double (&v)[KP], int jj, const double2* cb0,
-                                               const double2* cb1,
-                                               std::integer_sequence<int, Ms...>) {
-  (jacobi_round_v<KP, Ms + 1>(v, jj, (Ms & 1) ? cb1 : cb0,
-                              std::make_integer_sequence<int, KP / 2>{}), ...);
-}
-
-// LDS per block: matrix area (input staging, rotation coefficients during
-// the sweeps, then V in natural layout, row stride KP+1) and a 5 x KP area
-// per matrix that holds b, then Lambda^-1 V^T b, then dX and dX V for up to
-// five of the nine components at a time.  One-wavefront blocks at KP = 32
-// use 19 KiB, so eight fit in a CU's 160 KiB.
+// LDS per block: the matrix area (input staging, then the Householder vectors
+// with row stride KP, then V in natural layout with row stride KP+1), a
+// 5 x KP area per matrix that holds b, then Lambda^-1 V^T b, then dX and dX V
+// for up to five of the nine components at a time, and the tridiagonal
+// (d, e), the reflector scalars tau and two broadcast vectors.
 constexpr int kCompGroup = 5;
 template <int KP>
 struct EvdLds {
@@ -254,9 +48,45 @@ struct EvdLds {
   static constexpr int S = KP + 1;   // row stride: 16 consecutive rows hit distinct banks
   double mat[G][KP * S];
   double dxu[G][kCompGroup][KP];
-  double lam[64];
-  int flag;
+  double d[G][KP];
+  double e[G][KP];
+  double tau[G][KP];
+  double vb[G][KP];
+  double wb[G][KP];
 };
+
+// Value of x held by lane `src` of this lane's KP-lane group.
+template <int KP>
+__device__ __forceinline__ double group_read(double x, int src) {
+  return __shfl(x, src, KP);
+}
+
+// An integer the compiler cannot see through: LDS addresses derived from it
+// are recomputed after each use point instead of being hoisted out of the
+// unrolled loops (where every one of them would hold a VGPR).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("v_mov_b32 %0, %1" : "=v"(x) : "v"(x));
+  return x;
+}
+
+// Maximum over aligned groups of G lanes (every lane of a group gets it).
+template <int G>
+__device__ __forceinline__ double group_max(double x) {
+  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
+  if constexpr (G >= 32) x = fmax(x, xor_lane<16>(x));
+  if constexpr (G >= 16) x = fmax(x, xor_lane<8>(x));
+  if constexpr (G >= 8) x = fmax(x, xor_lane<4>(x));
+  if constexpr (G >= 4) x = fmax(x, xor_lane<2>(x));
+  if constexpr (G >= 2) x = fmax(x, xor_lane<1>(x));
+  return x;
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate and one Newton-Raphson step.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
 
 // Q = alpha I + C (mode 0, upper blocks mirrored) or A (mode 1) into the
 // matrix area, padded rows = unit; b into dxu[0] (mode 0).
@@ -272,17 +102,23 @@ __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, i
     for (int c = 0; c < KP; ++c) M[jj * S + c] = 0.0;
     wave_lds_sync();
     if (valid) {
-      const double* Cp = e.C + (size_t)pl * NB * 256;
+      // all of this lane's loads first (NB * 256 / KP values), then the LDS writes
+      constexpr int PER = 256 / KP;
+      const double* Cp = e.C + (size_t)pl * NB * 256 + jj;
+      double val[NB * PER];
+#pragma unroll
+      for (int q = 0; q < NB * PER; ++q) val[q] = Cp[(q / PER) * 256 + (q % PER) * KP];
       int blk = 0;
 #pragma unroll
       for (int I = 0; I < NQ; ++I) {
 #pragma unroll
         for (int J = I; J < NQ; ++J) {
-          for (int t = jj; t < 256; t += KP) {
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            const int t = jj + q * KP;
             const int r = t >> 4, c = t & 15;
-            const double val = Cp[blk * 256 + t];
-            M[(16 * I + r) * S + 16 * J + c] = val;
-            if (I != J) M[(16 * J + c) * S + 16 * I + r] = val;
+            M[(16 * I + r) * S + 16 * J + c] = val[blk * PER + q];
+            if (I != J) M[(16 * J + c) * S + 16 * I + r] = val[blk * PER + q];
           }
           ++blk;
         }
@@ -306,30 +142,222 @@ __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, i
   }
 }
 
+
 template <int KP>
 __device__ __forceinline__ void load_rows(const double* M, int jj, double (&a)[KP]) {
   constexpr int S = KP + 1;
 #pragma unroll
-  for (int u = 0; u < KP; ++u) a[u] = M[jj * S + (jj ^ u)];
+  for (int u = 0; u < KP; ++u) a[u] = M[jj * S + u];
 }
 
-// Diagonal-layout rows (v[u] = V[jj][jj^u]) into the natural layout in LDS.
+// Householder tridiagonalization of the symmetric matrix whose row jj this
+// lane holds in a[].  Step i annihilates A[i+2:, i] with H_i = I - tau v v^T,
+// v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
+//   d_j = T[j][j] -> sh.d,  e_j = T[j+1][j] -> sh.e,  tau_i -> sh.tau,
+//   v of step i -> row i of the matrix area (row stride KP).
 template <int KP>
-__device__ __forceinline__ void store_rows(double* M, int jj, const double (&v)[KP]) {
-  constexpr int S = KP + 1;
+__device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
 #pragma unroll
-  for (int u = 0; u < KP; ++u) M[jj * S + (jj ^ u)] = v[u];
+  for (int i = 0; i < KP - 2; ++i) {
+    const int so = opaque(seg * KP);
+    double* vb = &sh.vb[0][0] + so;
+    double* wb = &sh.wb[0][0] + so;
+    const double x = a[i];                                   // A[jj][i]
+    const double alpha = group_read<KP>(x, i + 1);            // A[i+1][i]
+    const double sig = group_sum<KP>(jj > i + 1 ? x * x : 0.0);
+    const bool refl = sig != 0.0;                             // uniform per matrix
+    const double nrm = sqrt(fma(alpha, alpha, sig));
+    const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+    const double tau = refl ? (beta - alpha) / beta : 0.0;
+    const double inv = refl ? 1.0 / (alpha - beta) : 0.0;
+    const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
+    vb[jj] = vj;
+    wave_lds_sync();
+    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      if ((c & 1) == 0)
+        p0 = fma(a[c], vb[c], p0);
+      else
+        p1 = fma(a[c], vb[c], p1);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
+    const double p = jj > i ? (p0 + p1) * tau : 0.0;
+    const double K = 0.5 * tau * group_sum<KP>(p * vj);
+    const double w = fma(-K, vj, p);
+    wb[jj] = w;
+    wave_lds_sync();
+    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
+    // v is read again through a fresh offset rather than kept live from above
+    const int so2 = opaque(so);
+    const double* vb2 = &sh.vb[0][0] + so2;
+    const double* wb2 = &sh.wb[0][0] + so2;
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      a[c] -= fma(vj, wb2[c], w * vb2[c]);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
+    // nothing of the next step may be scheduled into this one (the
+    // interleaving would keep two copies of the row live)
+    __builtin_amdgcn_sched_barrier(0);
+    wave_lds_sync();
+    if (jj > i) a[i] = vj;
+    if (jj == i) {
+      sh.e[seg][i] = beta;
+      sh.tau[seg][i] = tau;
+    }
+  }
+  double dg = 0.0;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;
+  sh.d[seg][jj] = dg;
+  if (jj == KP - 2) sh.e[seg][KP - 2] = a[KP - 1];
+  if (jj == KP - 1) sh.e[seg][KP - 1] = 0.0;
+  double* Vr = sh.mat[seg];
+#pragma unroll
+  for (int i = 0; i < KP - 2; ++i) Vr[i * KP + jj] = jj > i ? a[i] : 0.0;
+  wave_lds_sync();
 }
 
+// Row jj of H = H_0 H_1 ... H_{n-3} (so that Q = H T H^T), accumulated in
+// registers from the reflectors in the matrix area, then stored to the
+// matrix area in natural layout.
 template <int KP>
-__device__ __forceinline__ void init_identity(double (&v)[KP]) {
+__device__ __forceinline__ void form_reflector_product(double (&z)[KP], EvdLds<KP>& sh, int seg,
+                                                       int jj) {
+  constexpr int S = KP + 1;
+  double* M = sh.mat[seg];
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
-    // opaque constants: the compiler must not specialize the first sweep for V = I
-    double x = u == 0 ? 1.0 : 0.0;
-    asm volatile("" : "+v"(x));
-    v[u] = x;
+    double one = u == jj ? 1.0 : 0.0;
+    z[u] = one;
   }
+#pragma unroll
+  for (int i = 0; i < KP - 2; ++i) {
+    const double t = sh.tau[seg][i];
+    const double* v = &sh.mat[0][0] + opaque(seg * KP * (KP + 1)) + i * KP;
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      if ((c & 1) == 0)
+        d0 = fma(z[c], v[c], d0);
+      else
+        d1 = fma(z[c], v[c], d1);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
+    const double f = t * (d0 + d1);
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      z[c] = fma(-f, v[c], z[c]);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int u = 0; u < KP; ++u) M[jj * S + u] = z[u];
+  wave_lds_sync();
+}
+
+// Implicit QL with Wilkinson's shift on (d, e), rotations applied to the
+// columns of V (natural layout in the matrix area).  On return d holds the
+// eigenvalues and column j of V the eigenvector of d_j.  Returns false if the
+// matrix needed more than max_its QL iterations in total (the remaining
+// subdiagonal entries are then deflated one by one as they are).
+template <int KP>
+__device__ __forceinline__ bool ql_implicit(EvdLds<KP>& sh, int seg, int jj, int max_its) {
+  constexpr int S = KP + 1;
+  double* d = sh.d[seg];
+  double* e = sh.e[seg];
+  double* V = sh.mat[seg] + jj * S;      // this lane's row of V
+  const int sh0 = seg * KP;
+  const uint64_t lowmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
+  constexpr double kHalfEps = 0x1p-53;
+  // Deflation threshold relative to the norm of T, max_j |d_j| + |e_j| (as in
+  // EISPACK's tql2): the rounding noise that the reduction leaves in the
+  // subdiagonal of a tight eigenvalue cluster is of order eps |T|, so a test
+  // against the neighbouring diagonal entries alone can stall there.
+  double tn = fabs(d[jj]) + fabs(e[jj]);
+  tn = group_max<KP>(tn);
+  const double tol = kHalfEps * tn;
+  int l = 0, its = 0;
+  bool ok = true;
+  for (;;) {
+    wave_lds_sync();
+    // lane-parallel deflation test of e_jj (NaN counts as negligible so that
+    // a non-finite matrix still terminates)
+    const double ej = e[jj];
+    const bool small = jj == KP - 1 || !(fabs(ej) > tol);
+    const uint64_t sm = (__ballot(small) >> sh0) & lowmask;
+    const uint64_t ge = l < 64 ? ~0ull << l : 0ull;
+    const uint64_t ns = ~sm & ge & lowmask;
+    l = ns ? __builtin_ctzll(ns) : KP;
+    bool act = l < KP;
+    if (__ballot(act) == 0) break;
+    int m = act ? __builtin_ctzll(sm & (~0ull << l)) : 0;
+    if (act && ++its > max_its) {
+      ok = false;
+      e[l] = 0.0;                                          // out of iterations: deflate as is
+      act = false;
+    }
+    double dl = 0.0, g = 0.0;
+    if (act) {
+      dl = d[l];
+      const double dl1 = d[l + 1], el = e[l], dm = d[m];
+      g = (dl1 - dl) / (2.0 * el);
+      const double r = sqrt(fma(g, g, 1.0));
+      g = dm - dl + el / (g + (g >= 0.0 ? r : -r));
+    }
+    // sweep i = m-1 .. l: carries d[i+1] and the updated V[jj][i+1]
+    int i = m - 1;
+    double s = 1.0, c = 1.0, p = 0.0;
+    double di1 = act ? d[m] : 0.0;
+    double vi1 = act ? V[m] : 0.0;
+    double ei_n = act ? e[i] : 0.0, di_n = act ? d[i] : 0.0, vi_n = act ? V[i] : 0.0;
+    bool sw = act, under = false;
+    while (__ballot(sw)) {
+      if (sw) {
+        const double ei = ei_n, di = di_n, vi = vi_n;
+        const int ip = i > 0 ? i - 1 : 0;                 // prefetch the next step's operands
+        ei_n = e[ip];
+        di_n = d[ip];
+        vi_n = V[ip];
+        const double f = s * ei, b = c * ei;
+        const double rr = fma(f, f, g * g);
+        if (rr == 0.0) {
+          // f = g = 0: the sweep cannot continue; deflate at m and retry
+          d[i + 1] = di1 - p;
+          e[i + 1] = 0.0;
+          e[m] = 0.0;
+          V[i + 1] = vi1;
+          under = true;
+          sw = false;
+        } else {
+          const double ir = rsqrt_nr(rr);
+          e[i + 1] = rr * ir;
+          s = f * ir;
+          c = g * ir;
+          const double gg = di1 - p;
+          const double t = fma(di - gg, s, 2.0 * c * b);
+          p = s * t;
+          d[i + 1] = gg + p;
+          g = fma(c, t, -b);
+          V[i + 1] = fma(s, vi, c * vi1);
+          vi1 = fma(c, vi, -s * vi1);
+          di1 = di;
+          if (--i < l) sw = false;
+        }
+      }
+    }
+    if (act && !under) {
+      V[l] = vi1;
+      d[l] = dl - p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  wave_lds_sync();
+  return ok;
 }
 
 // Mode 1 output: eigenvalues and eigenvectors (V natural layout in M).
@@ -444,7 +472,6 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
   if (mine && !finite) atomicOr(e.status, kStatNonfinite);
 }
 
-// One wavefront holds both A and V rows of 64/KP matrices (KP = 16, 32).
 // The descriptor of the problem that owns slab-local point pl, with C and b
 // pointed at the slab and pt0 set so that pt0 + pl is the point within its
 // problem (every helper indexes C, b by pl and the ensemble by pt0 + pl).
@@ -460,8 +487,9 @@ __device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool&
   return e;
 }
 
+
 template <int KP>
-__global__ __launch_bounds__(64) void k_evd(BatchMap bm) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WAVES))) void k_evd(BatchMap bm) {
   constexpr int G = 64 / KP;
   __shared__ EvdLds<KP> sh;
   const int lane = lane_id();
@@ -469,22 +497,21 @@ __global__ __launch_bounds__(64) void k_evd(BatchMap bm) {
   const int pl = blockIdx.x * G + seg;
   bool valid;
   const EvdArgs e = evd_args_of(bm, pl, valid);
-  double* M = sh.mat[seg];
   stage_matrix<KP>(e, sh, seg, jj, pl, valid);
   wave_lds_sync();
-  double a[KP], v[KP];
-  load_rows<KP>(M, jj, a);
-  init_identity<KP>(v);
-  wave_lds_sync();
-  double2* cb0 = reinterpret_cast<double2*>(M);
-  const bool conv = jacobi_solve<KP>(a, v, jj, cb0, cb0 + KP, e.tol2, e.max_sweeps);
+  {
+    double a[KP];
+    load_rows<KP>(sh.mat[seg], jj, a);
+    wave_lds_sync();
+    tridiagonalize<KP>(a, sh, seg, jj);
+    form_reflector_product<KP>(a, sh, seg, jj);
+  }
+  const bool conv = ql_implicit<KP>(sh, seg, jj, e.max_its * KP);
   if (!conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
-  wave_lds_sync();
-  const double lam = a[0];
-  store_rows<KP>(M, jj, v);
+  const double lam = sh.d[seg][jj];
   wave_lds_sync();
   if (e.mode != 0) {
-    write_eig<KP>(e, M, jj, pl, valid, lam);
+    write_eig<KP>(e, sh.mat[seg], jj, pl, valid, lam);
     return;
   }
   if (e.prec == 0)
@@ -493,81 +520,11 @@ __global__ __launch_bounds__(64) void k_evd(BatchMap bm) {
     transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam);
 }
 
-// Two wavefronts per block: wavefront 0 holds A (and ends with the
-// eigenvalues), wavefront 1 holds V and does the transform.
-template <int KP>
-__global__ __launch_bounds__(128) void k_evd_split(BatchMap bm) {
-  constexpr int G = 64 / KP;
-  __shared__ EvdLds<KP> sh;
-  // wave-uniform role (readfirstlane makes the branch provably uniform, so A
-  // and V never share one wavefront's registers)
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = lane_id();
-  const int seg = lane / KP, jj = lane % KP;
-  const int pl = blockIdx.x * G + seg;
-  bool valid;
-  const EvdArgs e = evd_args_of(bm, pl, valid);
-  if (!valid) return;   // G = 1: the whole block shares one point (uniform exit, before any barrier)
-  double* M = sh.mat[seg];
-  if (wid == 0) stage_matrix<KP>(e, sh, seg, jj, pl, valid);
-  block_sync();
-  double2* cb0 = reinterpret_cast<double2*>(M);
-  double2* cb1 = cb0 + KP;
-  double lam = 1.0;
-  if (wid == 0) {
-    double a[KP];
-    load_rows<KP>(M, jj, a);
-    block_sync();                                  // matrix area becomes the coefficient buffers
-    for (int sweep = 0;; ++sweep) {
-      double off = 0.0;
-#pragma unroll
-      for (int u = 1; u < KP; ++u) off = fma(a[u], a[u], off);
-      const double dg = a[0] * a[0];
-      const bool conv = group_sum<KP>(off) <= e.tol2 * group_sum<KP>(dg);
-      const bool all = __ballot(!conv) == 0;
-      const bool stop = all || sweep >= e.max_sweeps;
-      if (stop && !all && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
-      if (lane == 0) sh.flag = stop ? 1 : 0;
-      block_sync();
-      if (stop) break;
-      jacobi_sweep_a<KP>(a, jj, cb0, cb1, std::make_integer_sequence<int, KP - 1>{});
-    }
-    lam = a[0];
-    sh.lam[lane] = lam;
-    block_sync();                                  // V written by wavefront 1
-    block_sync();                                  // eigenvalues published
-    if (e.mode != 0) write_eig<KP>(e, M, jj, pl, valid, lam);
-  } else {
-    double v[KP];
-    init_identity<KP>(v);
-    block_sync();
-    for (;;) {
-      block_sync();
-      if (sh.flag) break;
-      jacobi_sweep_v<KP>(v, jj, cb0, cb1, std::make_integer_sequence<int, KP - 1>{});
-    }
-    store_rows<KP>(M, jj, v);
-    block_sync();
-    block_sync();
-    lam = sh.lam[lane];
-    if (e.mode == 0) {
-      if (e.prec == 0)
-        transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam);
-      else
-        transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam);
-    }
-  }
-}
-
 template <int KP>
 hipError_t launch_evd_kp(const BatchMap& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const dim3 grid(ceil_div(a.n, 64 / KP));
-  if constexpr (KP == 64) {
-    hipLaunchKernelGGL(k_evd_split<KP>, grid, dim3(128), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(k_evd<KP>, grid, dim3(64), 0, s, a);
-  }
+  hipLaunchKernelGGL(k_evd<KP>, grid, dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
