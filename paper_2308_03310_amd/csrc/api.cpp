@@ -29,7 +29,6 @@ namespace {
 constexpr int kCell = 8;                       // observation-cell edge (lattice points)
 constexpr int kMaxDim = 32768;                 // keeps squared distances inside int32
 constexpr uint64_t kChunkBytes = 1ull << 30;   // Gram output (C, b) per slab
-constexpr int kQlMaxIts = 30;                  // QL iterations per matrix row, on average
 
 struct ProblemWs {
   letkf_problem p;
@@ -217,7 +216,6 @@ EvdArgs evd_desc(const ProblemWs& w, int* status) {
   ea.npts = w.npts;
   ea.alpha = (double)(p.k - 1) / p.infl;
   ea.sqrt_km1 = std::sqrt((double)(p.k - 1));
-  ea.max_its = kQlMaxIts;
   ea.xt = w.xt;
   ea.abort_flag = w.abort_flag;
   ea.status = status;
@@ -692,7 +690,6 @@ int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, d
   ea.mode = 1;
   ea.k = k;
   ea.npts = batch;
-  ea.max_its = kQlMaxIts;
   ea.A = a;
   ea.lam = lam;
   ea.vec = vec;

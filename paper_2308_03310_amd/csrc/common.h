@@ -72,6 +72,18 @@ __device__ __forceinline__ double group_sum(double x) {
   return x;
 }
 
+// Maximum over aligned groups of G lanes (every lane of a group gets it).
+template <int G>
+__device__ __forceinline__ double group_max(double x) {
+  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
+  if constexpr (G >= 32) x = fmax(x, xor_lane<16>(x));
+  if constexpr (G >= 16) x = fmax(x, xor_lane<8>(x));
+  if constexpr (G >= 8) x = fmax(x, xor_lane<4>(x));
+  if constexpr (G >= 4) x = fmax(x, xor_lane<2>(x));
+  if constexpr (G >= 2) x = fmax(x, xor_lane<1>(x));
+  return x;
+}
+
 // Block index remap so that consecutive logical blocks land on the same XCD
 // (blocks are dispatched round-robin over the 8 XCDs, each with its own L2).
 __device__ __forceinline__ int xcd_remap(int b, int nblocks) {

@@ -13,21 +13,16 @@
 //   1. Householder reduction to tridiagonal form T = H^T Q H (Golub & Van
 //      Loan, Matrix Computations, Sec. 8.3.1), one matrix row per lane in
 //      registers; the reflector of step i is broadcast through LDS and the
-//      symmetric rank-2 update A -= v w^T + w v^T runs in-lane.
-//   2. H = H_0 H_1 ... H_{n-3} accumulated row by row in registers, then
-//      stored to LDS (natural layout, row stride KP+1).
-//   3. Implicit QL iterations with Wilkinson's shift on T (Bowdler, Martin,
-//      Reinsch & Wilkinson 1968, "The QR and QL algorithms for symmetric
-//      matrices"), each plane rotation applied to the columns of H in LDS, so
-//      that H ends as the eigenvector matrix V.  Every lane of a matrix runs
-//      the same scalar rotation chain (the chain is uniform per matrix); the
-//      lane owns one row of V.  Deflation is tested lane-parallel (lane j
-//      tests the subdiagonal entry e_j) and resolved with a ballot.
-// Sizes below KP are padded with decoupled unit rows; their subdiagonal
-// entries are exactly zero, so no rotation ever couples them to the matrix.
+//      symmetric rank-2 update A -= v w^T + w v^T runs in-lane;
+//   2. eigenpairs of T by divide and conquer (k_dc.h): T = Q_T diag(lam) Q_T^T;
+//   3. back-transformation V = H Q_T = H_0 (H_1 (.. H_{n-3} Q_T)), one column
+//      of V per lane.
+// Sizes below KP are padded with decoupled unit rows: their couplings in T are
+// exactly zero, so every merge that involves them is trivial or deflates them.
 #pragma once
 #include "common.h"
 #include "launch.h"
+#include "k_dc.h"
 
 namespace letkf {
 
@@ -36,23 +31,30 @@ namespace letkf {
 #define LETKF_EVD_WAVES 2
 #endif
 
-// LDS per block: the matrix area (input staging, then the Householder vectors
-// with row stride KP, then V in natural layout with row stride KP+1), a
-// 5 x KP area per matrix that holds b, then Lambda^-1 V^T b, then dX and dX V
-// for up to five of the nine components at a time, and the tridiagonal
-// (d, e), the reflector scalars tau and two broadcast vectors.
+// LDS per block: the matrix area (input staging, then the merge matrices of
+// the divide and conquer, then the Householder vectors with row stride KP,
+// then V in natural layout with row stride KP+1), the tridiagonal (d, e), the
+// reflector scalars tau, and a union of the tridiagonalization's broadcast
+// vectors, the divide-and-conquer work arrays and the transform's 5 x KP area
+// (Lambda^-1 V^T b, then dX and dX V for up to five of the nine components at
+// a time).
 constexpr int kCompGroup = 5;
 template <int KP>
 struct EvdLds {
   static constexpr int G = 64 / KP;
   static constexpr int S = KP + 1;   // row stride: 16 consecutive rows hit distinct banks
   double mat[G][KP * S];
-  double dxu[G][kCompGroup][KP];
   double d[G][KP];
   double e[G][KP];
   double tau[G][KP];
-  double vb[G][KP];
-  double wb[G][KP];
+  union {
+    struct {                         // tridiagonalization: broadcast vectors
+      double vb[G][KP];
+      double wb[G][KP];
+    };
+    DcLds<KP> dc[G];                 // divide and conquer
+    double dxu[G][kCompGroup][KP];   // transform and update
+  };
 };
 
 // Value of x held by lane `src` of this lane's KP-lane group.
@@ -69,30 +71,11 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
-// Maximum over aligned groups of G lanes (every lane of a group gets it).
-template <int G>
-__device__ __forceinline__ double group_max(double x) {
-  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
-  if constexpr (G >= 32) x = fmax(x, xor_lane<16>(x));
-  if constexpr (G >= 16) x = fmax(x, xor_lane<8>(x));
-  if constexpr (G >= 8) x = fmax(x, xor_lane<4>(x));
-  if constexpr (G >= 4) x = fmax(x, xor_lane<2>(x));
-  if constexpr (G >= 2) x = fmax(x, xor_lane<1>(x));
-  return x;
-}
-
-// 1/sqrt(x) for x > 0: hardware estimate and one Newton-Raphson step.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x * y;
-  return fma(y, fma(-h, y, 0.5), y);
-}
-
 // Q = alpha I + C (mode 0, upper blocks mirrored) or A (mode 1) into the
-// matrix area, padded rows = unit; b into dxu[0] (mode 0).
+// matrix area, padded rows = unit; this lane's entry of b into bj (mode 0).
 template <int KP>
 __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
-                                             int pl, bool valid) {
+                                             int pl, bool valid, double& bj) {
   constexpr int NQ = KP / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   constexpr int S = EvdLds<KP>::S;
@@ -129,7 +112,7 @@ __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, i
       M[jj * S + jj] += e.alpha;
     else
       M[jj * S + jj] = 1.0;
-    sh.dxu[seg][0][jj] = (valid && jj < k) ? e.b[(size_t)pl * KP + jj] : 0.0;
+    bj = (valid && jj < k) ? e.b[(size_t)pl * KP + jj] : 0.0;
   } else {
     for (int c = 0; c < KP; ++c) {
       double val = c == jj ? 1.0 : 0.0;
@@ -154,7 +137,7 @@ __device__ __forceinline__ void load_rows(const double* M, int jj, double (&a)[K
 // lane holds in a[].  Step i annihilates A[i+2:, i] with H_i = I - tau v v^T,
 // v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
 //   d_j = T[j][j] -> sh.d,  e_j = T[j+1][j] -> sh.e,  tau_i -> sh.tau,
-//   v of step i -> row i of the matrix area (row stride KP).
+//   a[i] = v_jj of step i for i < jj (the lane's entries of the reflectors).
 template <int KP>
 __device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
 #pragma unroll
@@ -214,166 +197,76 @@ __device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, 
   sh.d[seg][jj] = dg;
   if (jj == KP - 2) sh.e[seg][KP - 2] = a[KP - 1];
   if (jj == KP - 1) sh.e[seg][KP - 1] = 0.0;
-  double* Vr = sh.mat[seg];
-#pragma unroll
-  for (int i = 0; i < KP - 2; ++i) Vr[i * KP + jj] = jj > i ? a[i] : 0.0;
   wave_lds_sync();
 }
 
-// Row jj of H = H_0 H_1 ... H_{n-3} (so that Q = H T H^T), accumulated in
-// registers from the reflectors in the matrix area, then stored to the
-// matrix area in natural layout.
+// V = H Q_T with H = H_0 H_1 .. H_{n-3}: q holds row jj of Q_T on entry.
+// Q_T goes through the matrix area to give this lane column jj, the
+// reflectors (a[i] = v_jj of step i) follow it there, and each lane applies
+// H_{n-3} .. H_0 to its column in registers; V leaves in the matrix area in
+// natural layout (row stride KP+1).
 template <int KP>
-__device__ __forceinline__ void form_reflector_product(double (&z)[KP], EvdLds<KP>& sh, int seg,
-                                                       int jj) {
+__device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a)[KP],
+                                               EvdLds<KP>& sh, int seg, int jj) {
   constexpr int S = KP + 1;
   double* M = sh.mat[seg];
 #pragma unroll
-  for (int u = 0; u < KP; ++u) {
-    double one = u == jj ? 1.0 : 0.0;
-    z[u] = one;
-  }
+  for (int u = 0; u < KP; ++u) M[jj * S + u] = q[u];
+  wave_lds_sync();
 #pragma unroll
-  for (int i = 0; i < KP - 2; ++i) {
+  for (int r = 0; r < KP; ++r) q[r] = M[r * S + jj];
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = jj > i ? a[i] : 0.0;
+  wave_lds_sync();
+#pragma unroll
+  for (int i = KP - 3; i >= 0; --i) {
     const double t = sh.tau[seg][i];
     const double* v = &sh.mat[0][0] + opaque(seg * KP * (KP + 1)) + i * KP;
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      if ((c & 1) == 0)
-        d0 = fma(z[c], v[c], d0);
+    for (int r = i + 1; r < KP; ++r) {
+      if ((r & 1) == 0)
+        d0 = fma(q[r], v[r], d0);
       else
-        d1 = fma(z[c], v[c], d1);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
+        d1 = fma(q[r], v[r], d1);
+      if ((r & 7) == 7) asm volatile("" ::: "memory");
     }
     const double f = t * (d0 + d1);
 #pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      z[c] = fma(-f, v[c], z[c]);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    for (int r = i + 1; r < KP; ++r) {
+      q[r] = fma(-f, v[r], q[r]);
+      if ((r & 7) == 7) asm volatile("" ::: "memory");
     }
   }
   wave_lds_sync();
 #pragma unroll
-  for (int u = 0; u < KP; ++u) M[jj * S + u] = z[u];
+  for (int r = 0; r < KP; ++r) M[r * S + jj] = q[r];
   wave_lds_sync();
 }
 
-// Implicit QL with Wilkinson's shift on (d, e), rotations applied to the
-// columns of V (natural layout in the matrix area).  On return d holds the
-// eigenvalues and column j of V the eigenvector of d_j.  Returns false if the
-// matrix needed more than max_its QL iterations in total (the remaining
-// subdiagonal entries are then deflated one by one as they are).
+// Mode 1 output: eigenvalues and eigenvectors (V natural layout in M).  For
+// k < KP the KP - k padding eigenpairs (unit vectors on the padded rows, which
+// the merges never couple to the matrix) are dropped and the k others are
+// written in column order.
 template <int KP>
-__device__ __forceinline__ bool ql_implicit(EvdLds<KP>& sh, int seg, int jj, int max_its) {
-  constexpr int S = KP + 1;
-  double* d = sh.d[seg];
-  double* e = sh.e[seg];
-  double* V = sh.mat[seg] + jj * S;      // this lane's row of V
-  const int sh0 = seg * KP;
-  const uint64_t lowmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
-  constexpr double kHalfEps = 0x1p-53;
-  // Deflation threshold relative to the norm of T, max_j |d_j| + |e_j| (as in
-  // EISPACK's tql2): the rounding noise that the reduction leaves in the
-  // subdiagonal of a tight eigenvalue cluster is of order eps |T|, so a test
-  // against the neighbouring diagonal entries alone can stall there.
-  double tn = fabs(d[jj]) + fabs(e[jj]);
-  tn = group_max<KP>(tn);
-  const double tol = kHalfEps * tn;
-  int l = 0, its = 0;
-  bool ok = true;
-  for (;;) {
-    wave_lds_sync();
-    // lane-parallel deflation test of e_jj (NaN counts as negligible so that
-    // a non-finite matrix still terminates)
-    const double ej = e[jj];
-    const bool small = jj == KP - 1 || !(fabs(ej) > tol);
-    const uint64_t sm = (__ballot(small) >> sh0) & lowmask;
-    const uint64_t ge = l < 64 ? ~0ull << l : 0ull;
-    const uint64_t ns = ~sm & ge & lowmask;
-    l = ns ? __builtin_ctzll(ns) : KP;
-    bool act = l < KP;
-    if (__ballot(act) == 0) break;
-    int m = act ? __builtin_ctzll(sm & (~0ull << l)) : 0;
-    if (act && ++its > max_its) {
-      ok = false;
-      e[l] = 0.0;                                          // out of iterations: deflate as is
-      act = false;
-    }
-    double dl = 0.0, g = 0.0;
-    if (act) {
-      dl = d[l];
-      const double dl1 = d[l + 1], el = e[l], dm = d[m];
-      g = (dl1 - dl) / (2.0 * el);
-      const double r = sqrt(fma(g, g, 1.0));
-      g = dm - dl + el / (g + (g >= 0.0 ? r : -r));
-    }
-    // sweep i = m-1 .. l: carries d[i+1] and the updated V[jj][i+1]
-    int i = m - 1;
-    double s = 1.0, c = 1.0, p = 0.0;
-    double di1 = act ? d[m] : 0.0;
-    double vi1 = act ? V[m] : 0.0;
-    double ei_n = act ? e[i] : 0.0, di_n = act ? d[i] : 0.0, vi_n = act ? V[i] : 0.0;
-    bool sw = act, under = false;
-    while (__ballot(sw)) {
-      if (sw) {
-        const double ei = ei_n, di = di_n, vi = vi_n;
-        const int ip = i > 0 ? i - 1 : 0;                 // prefetch the next step's operands
-        ei_n = e[ip];
-        di_n = d[ip];
-        vi_n = V[ip];
-        const double f = s * ei, b = c * ei;
-        const double rr = fma(f, f, g * g);
-        if (rr == 0.0) {
-          // f = g = 0: the sweep cannot continue; deflate at m and retry
-          d[i + 1] = di1 - p;
-          e[i + 1] = 0.0;
-          e[m] = 0.0;
-          V[i + 1] = vi1;
-          under = true;
-          sw = false;
-        } else {
-          const double ir = rsqrt_nr(rr);
-          e[i + 1] = rr * ir;
-          s = f * ir;
-          c = g * ir;
-          const double gg = di1 - p;
-          const double t = fma(di - gg, s, 2.0 * c * b);
-          p = s * t;
-          d[i + 1] = gg + p;
-          g = fma(c, t, -b);
-          V[i + 1] = fma(s, vi, c * vi1);
-          vi1 = fma(c, vi, -s * vi1);
-          di1 = di;
-          if (--i < l) sw = false;
-        }
-      }
-    }
-    if (act && !under) {
-      V[l] = vi1;
-      d[l] = dl - p;
-      e[l] = g;
-      e[m] = 0.0;
-    }
-  }
-  wave_lds_sync();
-  return ok;
-}
-
-// Mode 1 output: eigenvalues and eigenvectors (V natural layout in M).
-template <int KP>
-__device__ __forceinline__ void write_eig(const EvdArgs& e, const double* M, int jj, int pl,
-                                          bool valid, double lam) {
+__device__ __forceinline__ void write_eig(const EvdArgs& e, const double* M, int seg, int jj,
+                                          int pl, bool valid, double lam) {
   const int k = e.k;
-  if (valid && jj < k) {
-    e.lam[(size_t)pl * k + jj] = lam;
-    for (int r = 0; r < k; ++r) e.vec[((size_t)pl * k + r) * k + jj] = M[r * (KP + 1) + jj];
+  bool real = true;
+  for (int r = k; r < KP; ++r) real = real && M[r * (KP + 1) + jj] == 0.0;
+  const uint64_t lowmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
+  const uint64_t mask = (__ballot(real) >> (seg * KP)) & lowmask;
+  const int slot = __popcll(mask & ((1ull << jj) - 1ull));
+  if (valid && real && slot < k) {
+    e.lam[(size_t)pl * k + slot] = lam;
+    for (int r = 0; r < k; ++r) e.vec[((size_t)pl * k + r) * k + slot] = M[r * (KP + 1) + jj];
   }
 }
 
 // Mode 0: transform and in-place update of the point's nine components,
 // from V (natural layout in M, row stride KP+1), this lane's eigenvalue lam
-// and b (in dxu[0]).  Row reads M[jj][c] and column reads M[m][jj] are both
+// and this lane's entry of b.  Row reads M[jj][c] and column reads M[m][jj] are both
 // bank-conflict free within 16-lane groups.
 // T = double: FP64 contractions.  T = float: the reduced-precision forms —
 // V, b, dX, U and the weights are rounded to FP32 or BF16 (e.prec) as
@@ -388,7 +281,7 @@ __device__ __forceinline__ float opnd<float>(double x, int prec) { return round_
 
 template <int KP, typename T>
 __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
-                                                 int pl, bool valid, double lam) {
+                                                 int pl, bool valid, double lam, double bj) {
   const int prec = e.prec;
   constexpr int S = KP + 1;
   const int k = e.k;
@@ -396,6 +289,8 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
   const double* Mrow = M + jj * S;
   // z = Lambda^-1 V^T b  (lane jj = column jj)
   double* bz = sh.dxu[seg][0];
+  bz[jj] = bj;
+  wave_lds_sync();
   T z = 0;
 #pragma unroll 4
   for (int r = 0; r < KP; ++r) z = fma(opnd<T>(M[r * S + jj], prec), opnd<T>(bz[r], prec), z);
@@ -497,27 +392,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   const int pl = blockIdx.x * G + seg;
   bool valid;
   const EvdArgs e = evd_args_of(bm, pl, valid);
-  stage_matrix<KP>(e, sh, seg, jj, pl, valid);
+  double bj = 0.0;
+  stage_matrix<KP>(e, sh, seg, jj, pl, valid, bj);
   wave_lds_sync();
-  {
-    double a[KP];
-    load_rows<KP>(sh.mat[seg], jj, a);
-    wave_lds_sync();
-    tridiagonalize<KP>(a, sh, seg, jj);
-    form_reflector_product<KP>(a, sh, seg, jj);
-  }
-  const bool conv = ql_implicit<KP>(sh, seg, jj, e.max_its * KP);
+  double a[KP], q[KP];
+  load_rows<KP>(sh.mat[seg], jj, a);
+  wave_lds_sync();
+  tridiagonalize<KP>(a, sh, seg, jj);
+  const bool conv = dc_tridiagonal<KP>(q, sh.dc[seg], sh.d[seg], sh.e[seg], sh.mat[seg], jj);
   if (!conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
-  const double lam = sh.d[seg][jj];
+  const double lam = sh.dc[seg].lam[jj];
   wave_lds_sync();
+  back_transform<KP>(q, a, sh, seg, jj);
   if (e.mode != 0) {
-    write_eig<KP>(e, sh.mat[seg], jj, pl, valid, lam);
+    write_eig<KP>(e, sh.mat[seg], seg, jj, pl, valid, lam);
     return;
   }
   if (e.prec == 0)
-    transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam);
+    transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam, bj);
   else
-    transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam);
+    transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam, bj);
 }
 
 template <int KP>
