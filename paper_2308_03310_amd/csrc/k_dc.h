@@ -50,7 +50,7 @@ struct DcLds {
 };
 
 constexpr double kDcEps = 0x1p-52;
-constexpr int kSecularMaxIts = 64;
+constexpr int kSecularMaxIts = 48;
 
 // The root in (lo, hi) of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  with p1 < p2,
 // B1, B2 >= 0 (the function rises from -inf to +inf between the poles);
@@ -68,84 +68,105 @@ __device__ __forceinline__ double two_pole_root(double c0, double B1, double B2,
   return (r1 > p1 && r1 < p2) ? r1 : r2;
 }
 
-// Root i (0-based) of 1/rho + sum_{j<K} w_j^2/(d_j - lambda) = 0, d ascending
-// (LDS, K entries), rho > 0, every w_j != 0.  Returns the origin pole index
-// and tau with lambda = d[org] + tau; *its receives the iteration count.
+// 1/x for finite x != 0 of moderate size: hardware estimate and two
+// Newton-Raphson steps.
+__device__ __forceinline__ double frcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// Pole value of an unused slot of the padded secular arrays (its weight is
+// zero, so every term it contributes is exactly zero).
+constexpr double kFarPole = 1e300;
+
+// Root i (0-based) of 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over the S slots
+// of d, w (LDS; slots >= K padded with d = kFarPole, w = 0), d ascending on
+// the first K slots, rho > 0, w_j != 0 for j < K.  Returns the origin pole
+// index with lambda = d[org] + tau_out; conv is cleared if the iteration
+// limit was hit.
+template <int S>
 __device__ __forceinline__ int secular_root(const double* d, const double* w, int K, int i,
-                                            double rho, double& tau_out, int& its) {
+                                            double rho, double& tau_out, bool& conv) {
   const double irho = 1.0 / rho;
-  double lo, hi;
-  int org;
-  if (i < K - 1) {
-    const double di = d[i];
-    const double mid = 0.5 * (d[i + 1] - di);
-    double f = irho;
-    for (int j = 0; j < K; ++j) f += w[j] * w[j] / ((d[j] - di) - mid);
-    if (f >= 0.0) {
-      org = i;
-      lo = 0.0;
-      hi = mid;
-    } else {
-      org = i + 1;
-      lo = -mid;
-      hi = 0.0;
-    }
-  } else {
-    double s = 0.0;
-    for (int j = 0; j < K; ++j) s += w[j] * w[j];
-    org = K - 1;
-    lo = 0.0;
-    hi = rho * s * (1.0 + 8.0 * kDcEps);
+  const bool last = i == K - 1;
+  const double di = d[i];
+  const double di1 = last ? di : d[i + 1];
+  double s2 = 0.0;
+#pragma unroll 8
+  for (int j = 0; j < S; ++j) s2 = fma(w[j], w[j], s2);
+  // probe point: the interval midpoint (last root: halfway to d + rho |w|^2)
+  const double half = last ? 0.5 * rho * s2 : 0.5 * (di1 - di);
+  const double lm = di + half;
+  double fm = irho, ti = 0.0, ti1 = 0.0;
+#pragma unroll 8
+  for (int j = 0; j < S; ++j) {
+    const double t = w[j] * w[j] * frcp(d[j] - lm);
+    fm += t;
+    ti = j == i ? t : ti;
+    ti1 = j == i + 1 ? t : ti1;
   }
-  const double dorg = d[org];
-  const double pi = d[i] - dorg;                         // pole i, shifted
-  const double pi1 = i + 1 < K ? d[i + 1] - dorg : 0.0;  // pole i+1 (interior roots)
-  const double pm1 = i > 0 ? d[i - 1] - dorg : 0.0;      // pole i-1 (last root)
-  // start: the nearest poles exact, the other terms frozen at the midpoint
+  int org;
+  double lo, hi;
+  if (last) {
+    org = i;
+    lo = 0.0;
+    hi = rho * s2 * (1.0 + 8.0 * kDcEps);
+  } else if (fm >= 0.0) {
+    org = i;
+    lo = 0.0;
+    hi = half;
+  } else {
+    org = i + 1;
+    lo = -half;
+    hi = 0.0;
+  }
+  const double dorg = last || fm >= 0.0 ? di : di1;
+  const double pi = di - dorg, pi1 = di1 - dorg;
+  const double pm1 = i > 0 ? d[i - 1] - dorg : 0.0;
+  const double wi2 = w[i] * w[i];
+  const double wi12 = last ? 0.0 : w[i + 1] * w[i + 1];
+  // start: the nearest poles exact, the other terms frozen at the probe point
   double tau;
   {
-    const double tm = 0.5 * (lo + hi);
-    double rest = irho;
-    const int e1 = i, e2 = i < K - 1 ? i + 1 : i;
-    for (int j = 0; j < K; ++j)
-      if (j != e1 && j != e2) rest += w[j] * w[j] / ((d[j] - dorg) - tm);
-    double t0;
-    if (i < K - 1)
-      t0 = two_pole_root(rest, w[i] * w[i], w[i + 1] * w[i + 1], pi, pi1);
-    else
-      t0 = rest > 0.0 ? pi + w[i] * w[i] / rest : __builtin_nan("");
-    tau = (t0 > lo && t0 < hi) ? t0 : tm;
+    const double rest = fm - ti - ti1;
+    const double t0 = last ? (rest > 0.0 ? pi + wi2 / rest : __builtin_nan(""))
+                           : two_pole_root(rest, wi2, wi12, pi, pi1);
+    tau = (t0 > lo && t0 < hi) ? t0 : 0.5 * (lo + hi);
   }
-  its = 0;
-  for (int it = 1; it <= kSecularMaxIts; ++it) {
-    its = it;
-    // psi: terms j <= i, phi: terms j > i (for the last root psi2 = j < K-1)
+  conv = false;
+  for (int it = 0; it < kSecularMaxIts; ++it) {
+    // psi: terms j <= i, phi: terms j > i; ps2: terms j < K-1 (last root)
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, ps2 = 0.0, dps2 = 0.0;
-    for (int j = 0; j < K; ++j) {
-      const double r = (d[j] - dorg) - tau;
-      const double t = w[j] / r;
+#pragma unroll 8
+    for (int j = 0; j < S; ++j) {
+      const double t = w[j] * frcp((d[j] - dorg) - tau);
       const double tw = t * w[j], t2 = t * t;
-      if (j <= i) {
-        psi += tw;
-        dpsi += t2;
-      } else {
-        phi += tw;
-        dphi += t2;
-      }
-      if (j < K - 1) {
-        ps2 += tw;
-        dps2 += t2;
-      }
+      const bool le = j <= i;
+      psi += le ? tw : 0.0;
+      dpsi += le ? t2 : 0.0;
+      phi += le ? 0.0 : tw;
+      dphi += le ? 0.0 : t2;
+      ps2 += j < K - 1 ? tw : 0.0;
+      dps2 += j < K - 1 ? t2 : 0.0;
     }
     const double f = irho + psi + phi;
-    if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(psi) + fabs(phi))) break;
+    if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(psi) + fabs(phi))) {
+      conv = true;
+      break;
+    }
     if (f < 0.0)
       lo = tau;
     else
       hi = tau;
-    if (hi - lo <= 2.0 * kDcEps * fmax(fabs(lo), fabs(hi))) break;
+    if (hi - lo <= 2.0 * kDcEps * fmax(fabs(lo), fabs(hi))) {
+      conv = true;
+      break;
+    }
     double tn;
-    if (i < K - 1) {
+    if (!last) {
       const double g1 = pi - tau, g2 = pi1 - tau;
       const double B1 = dpsi * g1 * g1, A1 = psi - dpsi * g1;
       const double B2 = dphi * g2 * g2, A2 = phi - dphi * g2;
@@ -160,14 +181,14 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
       // pole's own term exact; the wanted root is the larger one
       const double g1 = pm1 - tau;
       const double B1 = dps2 * g1 * g1, A1 = ps2 - dps2 * g1;
-      const double B2 = w[i] * w[i];
       const double c0 = irho + A1;
       tn = __builtin_nan("");
       if (c0 > 0.0) {
-        const double a = c0, b = -(c0 * (pm1 + pi) + B1 + B2), c = c0 * pm1 * pi + B1 * pi + B2 * pm1;
-        const double disc = fmax(b * b - 4.0 * a * c, 0.0);
-        const double q = -0.5 * (b + (b >= 0.0 ? sqrt(disc) : -sqrt(disc)));
-        const double r1 = q / a, r2 = q != 0.0 ? c / q : r1;
+        const double aa = c0, bb = -(c0 * (pm1 + pi) + B1 + wi2);
+        const double cc = c0 * pm1 * pi + B1 * pi + wi2 * pm1;
+        const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
+        const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+        const double r1 = q / aa, r2 = q != 0.0 ? cc / q : r1;
         tn = fmax(r1, r2);
       }
     }
@@ -180,8 +201,8 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
 // One merge level S for every block of the matrix at once.  Lane jj (row jj
 // of T) is position t = jj % S of block a = jj - t.  qs[0..S/2) holds, on
 // entry, row jj of the child's eigenvector matrix restricted to the child's
-// columns; on exit (S < KP) qs[0..S) holds it for the merged block.  At
-// S == KP the full row is returned in qs[0..KP).  W is this matrix's LDS
+// columns; on exit it holds row jj of the merged block's eigenvector matrix
+// restricted to the block's columns (qs[0..S)).  W is this matrix's LDS
 // scratch for the merge matrices (KP * (KP + 1) doubles).
 template <int KP, int S>
 __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const double* e_orig,
@@ -191,6 +212,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   const int t = jj & (S - 1);
   const int a = jj - t;
   const int m = a + H;
+  const int sh0 = (lane_id() & ~(S - 1));    // first lane of this block in the wavefront
   double* Wb = W + (a / S) * S * WS;         // this block's merge matrix
   // z: last row of the left child, first row of the right child
   if (jj == m - 1) {
@@ -213,6 +235,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   const double w = trivial ? 0.0 : z / sqrt(nz2);
   // sort the poles (ties by index)
   int rank = 0;
+#pragma unroll 8
   for (int u = 0; u < S; ++u) {
     const double Du = L.dt[a + u];
     rank += (Du < D || (Du == D && u < t)) ? 1 : 0;
@@ -222,61 +245,72 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   L.pm[a + rank] = t;
   const double tol = 8.0 * kDcEps * fmax(group_max<S>(fabs(D)), rho);
   wave_lds_sync();
-  // deflation scan (sequential, one lane per block)
+  // deflation: negligible weights (lane-parallel), then pairs of close poles
+  // (a sequential scan by one lane over the sorted order)
+  const bool small = !(fabs(rho * L.ws[a + t]) > tol);
+  L.inv[a + t] = small ? -1 : 0;
+  if (small) L.ws[a + t] = 0.0;
+  wave_lds_sync();
   if (t == 0 && !trivial) {
-    int prev = -1, K = 0, nrot = 0;
+    int prev = -1, nrot = 0;
+    double dp = 0.0, wp = 0.0;
+#pragma unroll 8
     for (int k = 0; k < S; ++k) {
-      double wk = L.ws[a + k];
-      if (fabs(rho * wk) <= tol) {
-        L.ws[a + k] = 0.0;
-        L.inv[a + k] = -1;
-        continue;
-      }
-      L.inv[a + k] = 0;
-      if (prev >= 0) {
-        const double wp = L.ws[a + prev];
-        const double tt = sqrt(fma(wp, wp, wk * wk));
-        const double c = wk / tt, s = wp / tt;
-        const double dp = L.ds[a + prev], dj = L.ds[a + k];
-        if (fabs((dj - dp) * c * s) <= tol) {
-          L.ds[a + prev] = fma(c * c, dp, s * s * dj);
-          L.ds[a + k] = fma(s * s, dp, c * c * dj);
+      const double wk = L.ws[a + k], dk = L.ds[a + k];
+      if (L.inv[a + k] >= 0) {
+        bool rot = false;
+        double c = 0.0, sn = 0.0, tt = 0.0;
+        if (prev >= 0) {
+          tt = sqrt(fma(wp, wp, wk * wk));
+          c = wk / tt;
+          sn = wp / tt;
+          rot = fabs((dk - dp) * c * sn) <= tol;
+        }
+        if (rot) {
+          L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
           L.ws[a + prev] = 0.0;
-          L.ws[a + k] = tt;
           L.inv[a + prev] = -1;
           L.rp[a + nrot] = prev;
           L.rj[a + nrot] = k;
           L.rc[a + nrot] = c;
-          L.rs[a + nrot] = s;
+          L.rs[a + nrot] = sn;
           ++nrot;
+          dp = fma(sn * sn, dp, c * c * dk);
+          wp = tt;
+          L.ds[a + k] = dp;
+          L.ws[a + k] = wp;
+        } else {
+          dp = dk;
+          wp = wk;
         }
-      }
-      prev = k;
-    }
-    for (int k = 0; k < S; ++k) {
-      if (L.inv[a + k] >= 0) {
-        L.inv[a + k] = K;
-        L.kp[a + K] = k;
-        ++K;
+        prev = k;
       }
     }
-    L.nk[a] = K;
     L.nr[a] = nrot;
   }
   wave_lds_sync();
-  const int K = trivial ? 0 : L.nk[a];
-  if (t < K) {
-    const int sp = L.kp[a + t];
-    L.dk[a + t] = L.ds[a + sp];
-    L.wk[a + t] = L.ws[a + sp];
+  // keep list: non-deflated sorted positions in order
+  const bool keep = !trivial && L.inv[a + t] >= 0;
+  const uint64_t kmask = (__ballot(keep) >> sh0) & (S == 64 ? ~0ull : ((1ull << S) - 1ull));
+  const int K = __popcll(kmask);
+  const int kidx = __popcll(kmask & ((1ull << t) - 1ull));
+  if (keep) {
+    L.inv[a + t] = kidx;
+    L.kp[a + kidx] = t;
+    L.dk[a + kidx] = L.ds[a + t];
+    L.wk[a + kidx] = L.ws[a + t];
+  }
+  if (t >= K) {                                    // padding of the secular arrays
+    L.dk[a + t] = kFarPole;
+    L.wk[a + t] = 0.0;
   }
   wave_lds_sync();
   // secular roots, one per lane
   if (t < K) {
     double tau;
-    int its;
-    const int org = secular_root(L.dk + a, L.wk + a, K, t, rho, tau, its);
-    if (its >= kSecularMaxIts) ok = false;
+    bool conv;
+    const int org = secular_root<S>(L.dk + a, L.wk + a, K, t, rho, tau, conv);
+    if (!conv) ok = false;
     L.ro[a + t] = org;
     L.rt[a + t] = tau;
   }
@@ -285,16 +319,21 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   if (t < K) {
     const double dj = L.dk[a + t];
     double prod = 1.0 / rho;
-    for (int i = 0; i < K; ++i) {
-      const double num = (L.dk[a + L.ro[a + i]] - dj) + L.rt[a + i];
-      prod *= i == t ? num : num / (L.dk[a + i] - dj);
+#pragma unroll 8
+    for (int i = 0; i < S; ++i) {
+      if (i < K) {
+        const double num = (L.dk[a + L.ro[a + i]] - dj) + L.rt[a + i];
+        prod *= i == t ? num : num * frcp(L.dk[a + i] - dj);
+      }
     }
     const double zr = sqrt(fmax(prod, 0.0));
     L.zh[a + t] = L.wk[a + t] >= 0.0 ? zr : -zr;
   }
+  if (t >= K) L.zh[a + t] = 0.0;
   wave_lds_sync();
   // column t of the merge matrix (sorted eigenvalue order; rows block-local)
   double lam_new;
+#pragma unroll 8
   for (int r = 0; r < S; ++r) Wb[r * WS + t] = 0.0;
   if (trivial) {
     Wb[t * WS + t] = 1.0;
@@ -309,14 +348,18 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
       const double tau = L.rt[a + ti];
       const double dorg = L.dk[a + org];
       double nrm = 0.0;
-      for (int u = 0; u < K; ++u) {
-        const double v = L.zh[a + u] / ((L.dk[a + u] - dorg) - tau);
+#pragma unroll 8
+      for (int u = 0; u < S; ++u) {
+        const double v = L.zh[a + u] * frcp((L.dk[a + u] - dorg) - tau);
         nrm = fma(v, v, nrm);
       }
       const double inrm = 1.0 / sqrt(nrm);
-      for (int u = 0; u < K; ++u) {
-        const double v = L.zh[a + u] / ((L.dk[a + u] - dorg) - tau);
-        Wb[L.pm[a + L.kp[a + u]] * WS + t] = v * inrm;
+#pragma unroll 8
+      for (int u = 0; u < S; ++u) {
+        if (u < K) {
+          const double v = L.zh[a + u] * frcp((L.dk[a + u] - dorg) - tau);
+          Wb[L.pm[a + L.kp[a + u]] * WS + t] = v * inrm;
+        }
       }
       lam_new = dorg + tau;
     }
@@ -325,10 +368,10 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
     for (int q = nrot - 1; q >= 0; --q) {
       const int rpi = L.pm[a + L.rp[a + q]] * WS + t;
       const int rji = L.pm[a + L.rj[a + q]] * WS + t;
-      const double c = L.rc[a + q], s = L.rs[a + q];
+      const double c = L.rc[a + q], sn = L.rs[a + q];
       const double xp = Wb[rpi], xj = Wb[rji];
-      Wb[rpi] = fma(c, xp, s * xj);
-      Wb[rji] = fma(-s, xp, c * xj);
+      Wb[rpi] = fma(c, xp, sn * xj);
+      Wb[rji] = fma(-sn, xp, c * xj);
     }
   }
   L.lam[jj] = flip ? -lam_new : lam_new;
