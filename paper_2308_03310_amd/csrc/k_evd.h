@@ -138,59 +138,69 @@ __device__ __forceinline__ void load_rows(const double* M, int jj, double (&a)[K
 // v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
 //   d_j = T[j][j] -> sh.d,  e_j = T[j+1][j] -> sh.e,  tau_i -> sh.tau,
 //   a[i] = v_jj of step i for i < jj (the lane's entries of the reflectors).
+// Step I of the reduction (I is a compile-time index so that a[] stays in
+// registers at every size).
+template <int KP, int i>
+__device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
+  const int so = opaque(seg * KP);
+  double* vb = &sh.vb[0][0] + so;
+  double* wb = &sh.wb[0][0] + so;
+  const double x = a[i];                                   // A[jj][i]
+  const double alpha = group_read<KP>(x, i + 1);            // A[i+1][i]
+  const double sig = group_sum<KP>(jj > i + 1 ? x * x : 0.0);
+  const bool refl = sig != 0.0;                             // uniform per matrix
+  const double nrm = sqrt(fma(alpha, alpha, sig));
+  const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+  const double tau = refl ? (beta - alpha) / beta : 0.0;
+  const double inv = refl ? 1.0 / (alpha - beta) : 0.0;
+  const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
+  vb[jj] = vj;
+  wave_lds_sync();
+  // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+  double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+  for (int c = i + 1; c < KP; ++c) {
+    if ((c & 1) == 0)
+      p0 = fma(a[c], vb[c], p0);
+    else
+      p1 = fma(a[c], vb[c], p1);
+    if ((c & 7) == 7) asm volatile("" ::: "memory");
+  }
+  const double p = jj > i ? (p0 + p1) * tau : 0.0;
+  const double K = 0.5 * tau * group_sum<KP>(p * vj);
+  const double w = fma(-K, vj, p);
+  wb[jj] = w;
+  wave_lds_sync();
+  // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
+  // v is read again through a fresh offset rather than kept live from above
+  const int so2 = opaque(so);
+  const double* vb2 = &sh.vb[0][0] + so2;
+  const double* wb2 = &sh.wb[0][0] + so2;
+#pragma unroll
+  for (int c = i + 1; c < KP; ++c) {
+    a[c] -= fma(vj, wb2[c], w * vb2[c]);
+    if ((c & 7) == 7) asm volatile("" ::: "memory");
+  }
+  // nothing of the next step may be scheduled into this one (the
+  // interleaving would keep two copies of the row live)
+  __builtin_amdgcn_sched_barrier(0);
+  wave_lds_sync();
+  if (jj > i) a[i] = vj;
+  if (jj == i) {
+    sh.e[seg][i] = beta;
+    sh.tau[seg][i] = tau;
+  }
+}
+
+template <int KP, int... Is>
+__device__ __forceinline__ void tridiag_steps(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
+                                              std::integer_sequence<int, Is...>) {
+  (tridiag_step<KP, Is>(a, sh, seg, jj), ...);
+}
+
 template <int KP>
 __device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
-#pragma unroll
-  for (int i = 0; i < KP - 2; ++i) {
-    const int so = opaque(seg * KP);
-    double* vb = &sh.vb[0][0] + so;
-    double* wb = &sh.wb[0][0] + so;
-    const double x = a[i];                                   // A[jj][i]
-    const double alpha = group_read<KP>(x, i + 1);            // A[i+1][i]
-    const double sig = group_sum<KP>(jj > i + 1 ? x * x : 0.0);
-    const bool refl = sig != 0.0;                             // uniform per matrix
-    const double nrm = sqrt(fma(alpha, alpha, sig));
-    const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-    const double tau = refl ? (beta - alpha) / beta : 0.0;
-    const double inv = refl ? 1.0 / (alpha - beta) : 0.0;
-    const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
-    vb[jj] = vj;
-    wave_lds_sync();
-    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
-    double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      if ((c & 1) == 0)
-        p0 = fma(a[c], vb[c], p0);
-      else
-        p1 = fma(a[c], vb[c], p1);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
-    }
-    const double p = jj > i ? (p0 + p1) * tau : 0.0;
-    const double K = 0.5 * tau * group_sum<KP>(p * vj);
-    const double w = fma(-K, vj, p);
-    wb[jj] = w;
-    wave_lds_sync();
-    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
-    // v is read again through a fresh offset rather than kept live from above
-    const int so2 = opaque(so);
-    const double* vb2 = &sh.vb[0][0] + so2;
-    const double* wb2 = &sh.wb[0][0] + so2;
-#pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      a[c] -= fma(vj, wb2[c], w * vb2[c]);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
-    }
-    // nothing of the next step may be scheduled into this one (the
-    // interleaving would keep two copies of the row live)
-    __builtin_amdgcn_sched_barrier(0);
-    wave_lds_sync();
-    if (jj > i) a[i] = vj;
-    if (jj == i) {
-      sh.e[seg][i] = beta;
-      sh.tau[seg][i] = tau;
-    }
-  }
+  tridiag_steps<KP>(a, sh, seg, jj, std::make_integer_sequence<int, KP - 2>{});
   double dg = 0.0;
 #pragma unroll
   for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;
@@ -200,14 +210,64 @@ __device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, 
   wave_lds_sync();
 }
 
+// Packed position of reflector i's entry on row r (0 <= i < r < k): the
+// reflectors' entries below their unit element, reflector by reflector.
+__device__ __forceinline__ int refl_pos(int i, int r, int k) {
+  return i * k - i * (i + 1) / 2 + (r - i - 1);
+}
+
+// This lane's entries of the reflectors (a[i] = v_jj of step i, i < jj) to
+// global scratch rv (k (k - 1) / 2 doubles); rows >= k carry none.
+template <int KP>
+__device__ __forceinline__ void store_reflectors(const double (&a)[KP], double* rv, int k, int jj,
+                                                 bool valid) {
+  if (!valid || jj >= k) return;
+#pragma unroll
+  for (int i = 0; i < KP - 2; ++i)
+    if (i < jj) rv[refl_pos(i, jj, k)] = a[i];
+}
+
+// Applies reflector I (row I of the matrix area, stride KP) to this lane's
+// column q of Q_T (see back_transform).
+template <int KP, int i>
+__device__ __forceinline__ void apply_reflector(double (&q)[KP], EvdLds<KP>& sh, int seg) {
+  const double t = sh.tau[seg][i];
+  const double* v = &sh.mat[0][0] + opaque(seg * KP * (KP + 1)) + i * KP;
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int r = i + 1; r < KP; ++r) {
+    if ((r & 1) == 0)
+      d0 = fma(q[r], v[r], d0);
+    else
+      d1 = fma(q[r], v[r], d1);
+    if ((r & 7) == 7) asm volatile("" ::: "memory");
+  }
+  const double f = t * (d0 + d1);
+#pragma unroll
+  for (int r = i + 1; r < KP; ++r) {
+    q[r] = fma(-f, v[r], q[r]);
+    if ((r & 7) == 7) asm volatile("" ::: "memory");
+  }
+}
+
+template <int KP, int... Is>
+__device__ __forceinline__ void apply_reflectors(double (&q)[KP], EvdLds<KP>& sh, int seg,
+                                                 std::integer_sequence<int, Is...>) {
+  // H_{n-3} first, H_0 last
+  (apply_reflector<KP, KP - 3 - Is>(q, sh, seg), ...);
+}
+
 // V = H Q_T with H = H_0 H_1 .. H_{n-3}: q holds row jj of Q_T on entry.
-// Q_T goes through the matrix area to give this lane column jj, the
-// reflectors (a[i] = v_jj of step i) follow it there, and each lane applies
-// H_{n-3} .. H_0 to its column in registers; V leaves in the matrix area in
+// Q_T goes through the matrix area to give this lane column jj; the
+// reflectors follow it there as rows (stride KP), from this lane's registers
+// (a[i] = v_jj of step i, KP <= 32) or from the global scratch rv (KP = 64,
+// where the registers were needed during the divide and conquer); each lane
+// then applies H_{n-3} .. H_0 to its column.  V leaves in the matrix area in
 // natural layout (row stride KP+1).
 template <int KP>
 __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a)[KP],
-                                               EvdLds<KP>& sh, int seg, int jj) {
+                                               const double* rv, int k, EvdLds<KP>& sh, int seg,
+                                               int jj) {
   constexpr int S = KP + 1;
   double* M = sh.mat[seg];
 #pragma unroll
@@ -216,29 +276,18 @@ __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a
 #pragma unroll
   for (int r = 0; r < KP; ++r) q[r] = M[r * S + jj];
   wave_lds_sync();
+  if constexpr (KP <= 32) {
 #pragma unroll
-  for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = jj > i ? a[i] : 0.0;
-  wave_lds_sync();
+    for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = jj > i ? a[i] : 0.0;
+  } else {
+    double v[KP - 2];
 #pragma unroll
-  for (int i = KP - 3; i >= 0; --i) {
-    const double t = sh.tau[seg][i];
-    const double* v = &sh.mat[0][0] + opaque(seg * KP * (KP + 1)) + i * KP;
-    double d0 = 0.0, d1 = 0.0;
+    for (int i = 0; i < KP - 2; ++i) v[i] = (i < jj && jj < k) ? rv[refl_pos(i, jj, k)] : 0.0;
 #pragma unroll
-    for (int r = i + 1; r < KP; ++r) {
-      if ((r & 1) == 0)
-        d0 = fma(q[r], v[r], d0);
-      else
-        d1 = fma(q[r], v[r], d1);
-      if ((r & 7) == 7) asm volatile("" ::: "memory");
-    }
-    const double f = t * (d0 + d1);
-#pragma unroll
-    for (int r = i + 1; r < KP; ++r) {
-      q[r] = fma(-f, v[r], q[r]);
-      if ((r & 7) == 7) asm volatile("" ::: "memory");
-    }
+    for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = v[i];
   }
+  wave_lds_sync();
+  apply_reflectors<KP>(q, sh, seg, std::make_integer_sequence<int, KP - 2>{});
   wave_lds_sync();
 #pragma unroll
   for (int r = 0; r < KP; ++r) M[r * S + jj] = q[r];
@@ -395,15 +444,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   double bj = 0.0;
   stage_matrix<KP>(e, sh, seg, jj, pl, valid, bj);
   wave_lds_sync();
-  double a[KP], q[KP];
+  // KP = 64: scratch for the reflectors during the divide and conquer: this
+  // point's Gram output (mode 0, consumed by the staging above) or its
+  // eigenvector output (mode 1, written last)
+  double* rv = e.mode == 0 ? e.C + (size_t)pl * ((KP / 16) * (KP / 16 + 1) / 2) * 256 : e.vec + (size_t)pl * e.k * e.k;
+  double a[KP];
   load_rows<KP>(sh.mat[seg], jj, a);
   wave_lds_sync();
   tridiagonalize<KP>(a, sh, seg, jj);
+  if constexpr (KP > 32) store_reflectors<KP>(a, rv, e.k, jj, valid);
+  double q[KP];
   const bool conv = dc_tridiagonal<KP>(q, sh.dc[seg], sh.d[seg], sh.e[seg], sh.mat[seg], jj);
   if (!conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
   const double lam = sh.dc[seg].lam[jj];
   wave_lds_sync();
-  back_transform<KP>(q, a, sh, seg, jj);
+  back_transform<KP>(q, a, rv, e.k, sh, seg, jj);
   if (e.mode != 0) {
     write_eig<KP>(e, sh.mat[seg], seg, jj, pl, valid, lam);
     return;

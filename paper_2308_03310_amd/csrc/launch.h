@@ -66,7 +66,8 @@ struct EvdArgs {
   int pt0, npt;       // mode 0: points [pt0, pt0 + npt); mode 1: npt matrices
   double alpha;       // (k - 1) / rho
   double sqrt_km1;    // sqrt(k - 1)
-  const double* C;    // [npt][NB][256] upper 16x16 blocks of C (KP-padded)
+  double* C;          // [npt][NB][256] upper 16x16 blocks of C (KP-padded); reused as
+                      // scratch for the Householder reflectors once staged
   const double* b;    // [npt][KP]
   double* xt;         // point-major ensemble [npts][9][k], updated in place
   const double* A;    // mode 1: [npt][k][k]
