@@ -27,6 +27,8 @@ from paper_2308_03310_amd import synth  # noqa: E402
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
+# dense MFMA peaks of the Gram contraction by precision form
+PEAK_GRAM_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 
 def local_counts_regular(wl) -> np.ndarray:
@@ -83,6 +85,81 @@ def stored_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def timed_analyses(L, torch, wl, p, precision, steps, warmup, xb=None):
+    """Whole analyses of one problem at one precision form: returns (analyses/s,
+    ms per analysis, per-phase ms per analysis, launches per phase, the
+    analysis ensemble on the device)."""
+    dev = torch.device("cuda:0")
+    if xb is None:
+        xb = torch.from_numpy(p.xb).to(dev)
+    xa = torch.empty_like(xb)
+    obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl,
+                                        precision=precision)], flags=L.LETKF_FLAG_PHASE_TIMING)
+    try:
+        io = [L.make_io(0, xb, xa, obs)]
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            L.letkf_analyze(plan, io, stream)
+        torch.cuda.synchronize()
+        L.letkf_phase_times(plan)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            L.letkf_analyze(plan, io, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        calls, phase_ms, launches = L.letkf_phase_times(plan)
+        st = L.letkf_status(plan, sync=True)
+        if st != L.LETKF_OK:
+            raise SystemExit(f"{wl.name} precision {precision}: {L.letkf_strerror(st)}")
+        per_call = {k: v / max(calls, 1) for k, v in phase_ms.items()}
+    finally:
+        L.letkf_plan_destroy(plan)
+    return wl.nx * wl.ny / (ms / 1e3), ms, per_call, launches, xa
+
+
+def precision_form(L, torch, steps: int):
+    """The precision form on the 1024 x 1024, k = 64 workload: FP64 baseline,
+    FP32 and BF16 Gram/update contractions (FP64 eigensolve and eigenvalue
+    scaling in all three).  Errors are taken against the FP64 path over the
+    whole field (the FP64 path itself is held to the oracle by the tests)."""
+    wl = synth.WORKLOADS["grid1024_k64"]
+    p = synth.make_problem(wl)
+    xb = torch.from_numpy(p.xb).to(torch.device("cuda:0"))
+    gram_flops = algorithmic_flops(wl)["gram"]
+    res = {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "k": wl.k, "steps": steps,
+           "errors": "relative L2 over every entry of the analysis ensemble, against the "
+                     "FP64 path"}
+    base = ref = None
+    for name, prec in (("fp64", L.LETKF_PREC_FP64), ("fp32", L.LETKF_PREC_FP32),
+                       ("bf16", L.LETKF_PREC_BF16)):
+        rate, ms, ph, launches, xa = timed_analyses(L, torch, wl, p, prec, steps, 1, xb)
+        gram_tf = gram_flops / (ph["gram"] / 1e3) / 1e12
+        r = {"value": round(rate, 1), "unit": "grid-point analyses/s", "ms_per_analysis": round(ms, 3),
+             "gram_ms": round(ph["gram"], 4), "evd_update_ms": round(ph["evd_update"], 3),
+             "gram_tflops": round(gram_tf, 3),
+             "gram_frac_of_mfma_peak": round(gram_tf / PEAK_GRAM_TFLOPS[name], 4),
+             "gram_peak_tflops": PEAK_GRAM_TFLOPS[name]}
+        if base is None:
+            base, ref = r, xa
+        else:
+            r["rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(xa - ref) /
+                                        torch.linalg.vector_norm(ref))
+            r["increment_rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(xa - ref) /
+                                                  torch.linalg.vector_norm(ref - xb))
+            r["speedup_vs_fp64"] = round(rate / base["value"], 3)
+            r["gram_speedup_vs_fp64"] = round(base["gram_ms"] / r["gram_ms"], 3)
+            del xa
+        res[name] = r
+    del ref, xb
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, p, seconds: float):
     """The oracle, as it is, on a bounded sample of the workload's grid points."""
     from threadpoolctl import threadpool_limits
@@ -115,6 +192,12 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving run (0 to skip)")
     ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB before the "
+                         "timed loop (the known-size reference for HBM byte counters)")
+    ap.add_argument("--precision-steps", type=int, default=2,
+                    help="timed analyses per precision form on the 1024^2, k = 64 workload "
+                         "(0 to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -137,6 +220,14 @@ def main():
                         flags=L.LETKF_FLAG_PHASE_TIMING)
     io = [L.make_io(0, xb, xa, obs)]
     stream = torch.cuda.current_stream()
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 17            # doubles
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         L.letkf_analyze(plan, io, stream)
     torch.cuda.synchronize()
@@ -214,6 +305,10 @@ def main():
             out["serving"]["cycle"] = "50 BGK steps (tau 0.52, Kolmogorov forcing 1e-5) + analysis"
         finally:
             srv.close()
+    if args.precision_steps > 0:
+        del xb, xa, obs
+        torch.cuda.empty_cache()
+        out["precision_form"] = precision_form(L, torch, args.precision_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
