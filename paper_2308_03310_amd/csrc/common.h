@@ -58,29 +58,42 @@ __device__ __forceinline__ double xor_lane(double x) {
   return __hiloint2double(hi, lo);
 }
 
-// Butterfly sum over aligned groups of G lanes (G a power of two <= 64).
-// Every lane of a group receives the bitwise-identical total (IEEE addition
-// is commutative and the tree is symmetric).
+// Value of x from the lane that a DPP pattern selects within each row of 16
+// lanes (CDNA data-parallel primitives: a VALU move, no LDS round trip).
+//   0xB1 quad_perm [1,0,3,2]  (lane ^ 1)       0x4E quad_perm [2,3,0,1]  (lane ^ 2)
+//   0x141 row_half_mirror     (i <-> 7 - i)    0x140 row_mirror         (i <-> 15 - i)
+template <int CTRL>
+__device__ __forceinline__ double dpp_lane(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64).  Stages within
+// 16 lanes use DPP; wider ones the swizzle network (32) and ds_bpermute (64).
+// Every stage pairs lanes symmetrically and IEEE addition is commutative, and
+// after each stage all lanes of a sub-group hold the same bits, so every lane
+// of a group receives the bitwise-identical total.
 template <int G>
 __device__ __forceinline__ double group_sum(double x) {
-  if constexpr (G >= 64) x += xor_lane<32>(x);
+  if constexpr (G >= 2) x += dpp_lane<0xB1>(x);
+  if constexpr (G >= 4) x += dpp_lane<0x4E>(x);
+  if constexpr (G >= 8) x += dpp_lane<0x141>(x);
+  if constexpr (G >= 16) x += dpp_lane<0x140>(x);
   if constexpr (G >= 32) x += xor_lane<16>(x);
-  if constexpr (G >= 16) x += xor_lane<8>(x);
-  if constexpr (G >= 8) x += xor_lane<4>(x);
-  if constexpr (G >= 4) x += xor_lane<2>(x);
-  if constexpr (G >= 2) x += xor_lane<1>(x);
+  if constexpr (G >= 64) x += xor_lane<32>(x);
   return x;
 }
 
 // Maximum over aligned groups of G lanes (every lane of a group gets it).
 template <int G>
 __device__ __forceinline__ double group_max(double x) {
-  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
+  if constexpr (G >= 2) x = fmax(x, dpp_lane<0xB1>(x));
+  if constexpr (G >= 4) x = fmax(x, dpp_lane<0x4E>(x));
+  if constexpr (G >= 8) x = fmax(x, dpp_lane<0x141>(x));
+  if constexpr (G >= 16) x = fmax(x, dpp_lane<0x140>(x));
   if constexpr (G >= 32) x = fmax(x, xor_lane<16>(x));
-  if constexpr (G >= 16) x = fmax(x, xor_lane<8>(x));
-  if constexpr (G >= 8) x = fmax(x, xor_lane<4>(x));
-  if constexpr (G >= 4) x = fmax(x, xor_lane<2>(x));
-  if constexpr (G >= 2) x = fmax(x, xor_lane<1>(x));
+  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
   return x;
 }
 
