@@ -36,13 +36,14 @@ struct DcLds {
   double dk[KP];    // non-deflated poles (ascending)
   double wk[KP];    // non-deflated weights
   double rt[KP];    // secular roots: offset tau from the origin pole
+  double rd[KP];    // secular roots: origin pole value
   double zh[KP];    // recomputed weights zhat
   double rc[KP];    // deflation rotations: cosine
   double rs[KP];    //                       sine
   int pm[KP];       // sorted position -> block-local original index
   int kp[KP];       // non-deflated index -> sorted position
   int inv[KP];      // sorted position -> non-deflated index, -1 if deflated
-  int ro[KP];       // secular roots: origin pole (non-deflated index)
+  int rw[KP];       // non-deflated index -> block-local row of its eigenvector entry
   int rp[KP];       // deflation rotations: first sorted position
   int rj[KP];       //                       second sorted position
   int nk[KP];       // per block (at its base): non-deflated count
@@ -138,19 +139,25 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   }
   conv = false;
   for (int it = 0; it < kSecularMaxIts; ++it) {
-    // psi: terms j <= i, phi: terms j > i; ps2: terms j < K-1 (last root)
-    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, ps2 = 0.0, dps2 = 0.0;
+    // psi: terms j <= i, phi: terms j > i
+    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < S; ++j) {
+    for (int j = 0; j < i; ++j) {
       const double t = w[j] * frcp((d[j] - dorg) - tau);
-      const double tw = t * w[j], t2 = t * t;
-      const bool le = j <= i;
-      psi += le ? tw : 0.0;
-      dpsi += le ? t2 : 0.0;
-      phi += le ? 0.0 : tw;
-      dphi += le ? 0.0 : t2;
-      ps2 += j < K - 1 ? tw : 0.0;
-      dps2 += j < K - 1 ? t2 : 0.0;
+      psi = fma(t, w[j], psi);
+      dpsi = fma(t, t, dpsi);
+    }
+    const double ps2 = psi, dps2 = dpsi;          // terms j < i (the last root's model)
+    {
+      const double t = w[i] * frcp(pi - tau);
+      psi = fma(t, w[i], psi);
+      dpsi = fma(t, t, dpsi);
+    }
+#pragma unroll 8
+    for (int j = i + 1; j < K; ++j) {
+      const double t = w[j] * frcp((d[j] - dorg) - tau);
+      phi = fma(t, w[j], phi);
+      dphi = fma(t, t, dphi);
     }
     const double f = irho + psi + phi;
     if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(psi) + fabs(phi))) {
@@ -192,7 +199,16 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
         tn = fmax(r1, r2);
       }
     }
-    tau = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+    const bool inside = tn > lo && tn < hi;
+    const double tnew = inside ? tn : 0.5 * (lo + hi);
+    // a model step (not a bisection) this small has converged: the model is
+    // exact to second order, so the next step would move tau by an ulp
+    const bool done = inside && fabs(tnew - tau) <= 2.0 * kDcEps * fabs(tnew);
+    tau = tnew;
+    if (done) {
+      conv = true;
+      break;
+    }
   }
   tau_out = tau;
   return org;
@@ -297,6 +313,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   if (keep) {
     L.inv[a + t] = kidx;
     L.kp[a + kidx] = t;
+    L.rw[a + kidx] = L.pm[a + t];
     L.dk[a + kidx] = L.ds[a + t];
     L.wk[a + kidx] = L.ws[a + t];
   }
@@ -311,7 +328,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
     bool conv;
     const int org = secular_root<S>(L.dk + a, L.wk + a, K, t, rho, tau, conv);
     if (!conv) ok = false;
-    L.ro[a + t] = org;
+    L.rd[a + t] = L.dk[a + org];
     L.rt[a + t] = tau;
   }
   wave_lds_sync();
@@ -322,7 +339,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
 #pragma unroll 8
     for (int i = 0; i < S; ++i) {
       if (i < K) {
-        const double num = (L.dk[a + L.ro[a + i]] - dj) + L.rt[a + i];
+        const double num = (L.rd[a + i] - dj) + L.rt[a + i];
         prod *= i == t ? num : num * frcp(L.dk[a + i] - dj);
       }
     }
@@ -344,23 +361,18 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
       Wb[L.pm[a + t] * WS + t] = 1.0;
       lam_new = L.ds[a + t];
     } else {
-      const int org = L.ro[a + ti];
       const double tau = L.rt[a + ti];
-      const double dorg = L.dk[a + org];
+      const double dorg = L.rd[a + ti];
       double nrm = 0.0;
 #pragma unroll 8
-      for (int u = 0; u < S; ++u) {
+      for (int u = 0; u < K; ++u) {
         const double v = L.zh[a + u] * frcp((L.dk[a + u] - dorg) - tau);
         nrm = fma(v, v, nrm);
+        Wb[L.rw[a + u] * WS + t] = v;
       }
       const double inrm = 1.0 / sqrt(nrm);
 #pragma unroll 8
-      for (int u = 0; u < S; ++u) {
-        if (u < K) {
-          const double v = L.zh[a + u] * frcp((L.dk[a + u] - dorg) - tau);
-          Wb[L.pm[a + L.kp[a + u]] * WS + t] = v * inrm;
-        }
-      }
+      for (int u = 0; u < K; ++u) Wb[L.rw[a + u] * WS + t] *= inrm;
       lam_new = dorg + tau;
     }
     // deflation rotations, last first, on rows pm[p], pm[j] of this column
