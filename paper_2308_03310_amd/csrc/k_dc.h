@@ -53,11 +53,13 @@ struct DcLds {
 constexpr double kDcEps = 0x1p-52;
 constexpr int kSecularMaxIts = 48;
 
-// The root in (lo, hi) of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  with p1 < p2,
-// B1, B2 >= 0 (the function rises from -inf to +inf between the poles);
-// NaN if the quadratic gives none.
+// The root of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  (p1 < p2, B1, B2 >= 0: the
+// function rises from -inf to +inf between the poles) that lies in the
+// bracket (lo, hi) inside (p1, p2); NaN if neither root of the quadratic
+// does.  (With a tiny B the quadratic's other root sits just outside a pole
+// and can round to inside it, so the pole interval cannot pick the root.)
 __device__ __forceinline__ double two_pole_root(double c0, double B1, double B2, double p1,
-                                                double p2) {
+                                                double p2, double lo, double hi) {
   const double a = c0;
   const double b = -(c0 * (p1 + p2) + B1 + B2);
   const double c = c0 * p1 * p2 + B1 * p2 + B2 * p1;
@@ -66,7 +68,7 @@ __device__ __forceinline__ double two_pole_root(double c0, double B1, double B2,
   const double q = -0.5 * (b + (b >= 0.0 ? sqrt(disc) : -sqrt(disc)));
   const double r1 = q / a;
   const double r2 = q != 0.0 ? c / q : __builtin_nan("");
-  return (r1 > p1 && r1 < p2) ? r1 : r2;
+  return (r1 > lo && r1 < hi) ? r1 : r2;
 }
 
 // 1/x for finite x != 0 of moderate size: hardware estimate and two
@@ -134,33 +136,38 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   {
     const double rest = fm - ti - ti1;
     const double t0 = last ? (rest > 0.0 ? pi + wi2 / rest : __builtin_nan(""))
-                           : two_pole_root(rest, wi2, wi12, pi, pi1);
+                           : two_pole_root(rest, wi2, wi12, pi, pi1, lo, hi);
     tau = (t0 > lo && t0 < hi) ? t0 : 0.5 * (lo + hi);
   }
+  // Iteration on a two-pole model: the terms of the two poles nearest the
+  // root (e1 < e2) are kept exact, the far terms below e1 and above e2 are
+  // each replaced by a constant plus a multiple of the nearer model pole that
+  // matches their value and slope at tau (so no dominant term is ever
+  // subtracted from a sum that contains it).
+  const int e1 = last ? i - 1 : i;           // -1 when K == 1
+  const int e2 = last ? i : i + 1;
+  const double P1 = last ? pm1 : pi, P2 = last ? pi : pi1;
+  const double W1 = e1 >= 0 ? w[e1] * w[e1] : 0.0, W2 = w[e2] * w[e2];
   conv = false;
   for (int it = 0; it < kSecularMaxIts; ++it) {
-    // psi: terms j <= i, phi: terms j > i
-    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+    double pl = 0.0, dpl = 0.0, ph = 0.0, dph = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < i; ++j) {
+    for (int j = 0; j < e1; ++j) {
       const double t = w[j] * frcp((d[j] - dorg) - tau);
-      psi = fma(t, w[j], psi);
-      dpsi = fma(t, t, dpsi);
-    }
-    const double ps2 = psi, dps2 = dpsi;          // terms j < i (the last root's model)
-    {
-      const double t = w[i] * frcp(pi - tau);
-      psi = fma(t, w[i], psi);
-      dpsi = fma(t, t, dpsi);
+      pl = fma(t, w[j], pl);
+      dpl = fma(t, t, dpl);
     }
 #pragma unroll 8
-    for (int j = i + 1; j < K; ++j) {
+    for (int j = e2 + 1; j < K; ++j) {
       const double t = w[j] * frcp((d[j] - dorg) - tau);
-      phi = fma(t, w[j], phi);
-      dphi = fma(t, t, dphi);
+      ph = fma(t, w[j], ph);
+      dph = fma(t, t, dph);
     }
-    const double f = irho + psi + phi;
-    if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(psi) + fabs(phi))) {
+    const double g1 = P1 - tau, g2 = P2 - tau;
+    const double t1 = e1 >= 0 ? W1 * frcp(g1) : 0.0;
+    const double t2 = W2 * frcp(g2);
+    const double f = irho + pl + ph + t1 + t2;
+    if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(pl) + fabs(ph) + fabs(t1) + fabs(t2))) {
       conv = true;
       break;
     }
@@ -172,27 +179,19 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
       conv = true;
       break;
     }
+    const double c0 = irho + (pl - dpl * g1) + (ph - dph * g2);
+    const double B1 = W1 + dpl * g1 * g1, B2 = W2 + dph * g2 * g2;
     double tn;
     if (!last) {
-      const double g1 = pi - tau, g2 = pi1 - tau;
-      const double B1 = dpsi * g1 * g1, A1 = psi - dpsi * g1;
-      const double B2 = dphi * g2 * g2, A2 = phi - dphi * g2;
-      tn = two_pole_root(irho + A1 + A2, B1, B2, pi, pi1);
+      tn = two_pole_root(c0, B1, B2, P1, P2, lo, hi);
     } else if (K == 1) {
-      const double g1 = pi - tau;
-      const double B1 = dpsi * g1 * g1, A1 = psi - dpsi * g1;
-      const double c0 = irho + A1;
-      tn = c0 > 0.0 ? pi + B1 / c0 : __builtin_nan("");
+      tn = c0 > 0.0 ? P2 + B2 / c0 : __builtin_nan("");
     } else {
-      // last root: the terms j < K-1 modelled by a pole at pole K-2, the last
-      // pole's own term exact; the wanted root is the larger one
-      const double g1 = pm1 - tau;
-      const double B1 = dps2 * g1 * g1, A1 = ps2 - dps2 * g1;
-      const double c0 = irho + A1;
+      // last root: above both model poles, the larger root of the quadratic
       tn = __builtin_nan("");
       if (c0 > 0.0) {
-        const double aa = c0, bb = -(c0 * (pm1 + pi) + B1 + wi2);
-        const double cc = c0 * pm1 * pi + B1 * pi + wi2 * pm1;
+        const double aa = c0, bb = -(c0 * (P1 + P2) + B1 + B2);
+        const double cc = c0 * P1 * P2 + B1 * P2 + B2 * P1;
         const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
         const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
         const double r1 = q / aa, r2 = q != 0.0 ? cc / q : r1;

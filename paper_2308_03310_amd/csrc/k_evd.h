@@ -151,8 +151,8 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   const bool refl = sig != 0.0;                             // uniform per matrix
   const double nrm = sqrt(fma(alpha, alpha, sig));
   const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-  const double tau = refl ? (beta - alpha) / beta : 0.0;
-  const double inv = refl ? 1.0 / (alpha - beta) : 0.0;
+  const double tau = refl ? (beta - alpha) * frcp(beta) : 0.0;
+  const double inv = refl ? frcp(alpha - beta) : 0.0;
   const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
   vb[jj] = vj;
   wave_lds_sync();
