@@ -150,19 +150,40 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   const double W1 = e1 >= 0 ? w[e1] * w[e1] : 0.0, W2 = w[e2] * w[e2];
   conv = false;
   for (int it = 0; it < kSecularMaxIts; ++it) {
-    double pl = 0.0, dpl = 0.0, ph = 0.0, dph = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < e1; ++j) {
-      const double t = w[j] * frcp((d[j] - dorg) - tau);
-      pl = fma(t, w[j], pl);
-      dpl = fma(t, t, dpl);
+    // two partial sums per accumulator halve the dependent chain
+    double pl0 = 0.0, dpl0 = 0.0, pl1 = 0.0, dpl1 = 0.0;
+    double ph0 = 0.0, dph0 = 0.0, ph1 = 0.0, dph1 = 0.0;
+    int j = 0;
+#pragma unroll 4
+    for (; j + 1 < e1; j += 2) {
+      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
+      const double t1 = w[j + 1] * frcp((d[j + 1] - dorg) - tau);
+      pl0 = fma(t0, w[j], pl0);
+      dpl0 = fma(t0, t0, dpl0);
+      pl1 = fma(t1, w[j + 1], pl1);
+      dpl1 = fma(t1, t1, dpl1);
     }
-#pragma unroll 8
-    for (int j = e2 + 1; j < K; ++j) {
-      const double t = w[j] * frcp((d[j] - dorg) - tau);
-      ph = fma(t, w[j], ph);
-      dph = fma(t, t, dph);
+    if (j < e1) {
+      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
+      pl0 = fma(t0, w[j], pl0);
+      dpl0 = fma(t0, t0, dpl0);
     }
+    j = e2 + 1;
+#pragma unroll 4
+    for (; j + 1 < K; j += 2) {
+      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
+      const double t1 = w[j + 1] * frcp((d[j + 1] - dorg) - tau);
+      ph0 = fma(t0, w[j], ph0);
+      dph0 = fma(t0, t0, dph0);
+      ph1 = fma(t1, w[j + 1], ph1);
+      dph1 = fma(t1, t1, dph1);
+    }
+    if (j < K) {
+      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
+      ph0 = fma(t0, w[j], ph0);
+      dph0 = fma(t0, t0, dph0);
+    }
+    const double pl = pl0 + pl1, dpl = dpl0 + dpl1, ph = ph0 + ph1, dph = dph0 + dph1;
     const double g1 = P1 - tau, g2 = P2 - tau;
     const double t1 = e1 >= 0 ? W1 * frcp(g1) : 0.0;
     const double t2 = W2 * frcp(g2);
