@@ -155,6 +155,36 @@ typedef struct letkf_cycle_io {
 int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream);
 
 /*
+ * letkf_tune -- project autotuner for the plan's launch settings.  Runs the
+ * analyses io[0..n_io) (every problem once gives the batched form) with each
+ * candidate setting -- observation-cell edge 4, 8 or 16 lattice points (the
+ * tile of the local-observation search) x the Gram kernels in grid or
+ * persistent work-queue form -- times each on hip_stream with HIP events, and
+ * keeps the fastest in the plan for later letkf_analyze / letkf_cycle calls.
+ * Synchronizes the stream (not usable under graph capture).  On return the
+ * outputs hold one analysis made with the chosen setting; out (may be NULL)
+ * receives it.  Errors as letkf_analyze, plus LETKF_EDEVICE.
+ */
+typedef struct letkf_tuning {
+  int32_t cell;             /* observation-cell edge chosen */
+  int32_t gram_persistent;  /* 1: Gram kernels in persistent form */
+  double  ms_per_call;      /* measured time of one call with that setting */
+} letkf_tuning;
+
+int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream,
+               letkf_tuning* out);
+
+/*
+ * letkf_set_tuning -- apply a setting (from letkf_tune, e.g. kept from an
+ * earlier run) without timing anything: cell in {4, 8, 16}, gram_persistent
+ * in {0, 1}; ms_per_call is ignored.  Waits for the plan's last stream.
+ * Returns LETKF_EINVAL for other values.  Results depend on the cell edge
+ * only through the summation order of the Gram matrix (rounding level); the
+ * two Gram forms give bitwise-identical results.
+ */
+int letkf_set_tuning(letkf_plan_t plan, const letkf_tuning* t);
+
+/*
  * letkf_status -- device-detected status of the plan's calls since the last
  * letkf_status.  sync != 0 waits for the plan's last stream first (otherwise
  * the value reflects only completed work).  Returns LETKF_OK or the first

@@ -26,13 +26,15 @@ using namespace letkf;
 
 namespace {
 
-constexpr int kCell = 8;                       // observation-cell edge (lattice points)
+constexpr int kCell = 8;                       // default observation-cell edge (lattice points)
+constexpr int kCellMin = 4;                    // smallest cell edge letkf_tune tries
 constexpr int kMaxDim = 32768;                 // keeps squared distances inside int32
 constexpr uint64_t kChunkBytes = 1ull << 30;   // Gram output (C, b) per slab
 
 struct ProblemWs {
   letkf_problem p;
   int npts, kp, nb, ncx, ncy, ncells, nobs_alloc;
+  int cell;             // observation-cell edge in use (tunable)
   double* xt;
   int* obs_cell;
   int* perm;
@@ -125,6 +127,8 @@ struct letkf_plan_s {
   uint64_t bytes = 0;
   std::atomic<int> busy{0};
   hipStream_t last_stream = nullptr;
+  bool gram_persistent = false;     // Gram kernels in their persistent form (tunable)
+  int* queue = nullptr;             // device [kQueueSlots]: persistent-launch work counters
   // Phase timing: a ring of event sets, one set per timed call.
   static constexpr int kSlots = 256;
   bool timing = false;
@@ -153,14 +157,22 @@ struct letkf_plan_s {
 
 namespace {
 
+void set_cell(ProblemWs& w, int cell) {
+  w.cell = cell;
+  w.ncx = ceil_div(w.p.nx, cell);
+  w.ncy = ceil_div(w.p.ny, cell);
+  w.ncells = w.ncx * w.ncy;
+}
+
+// Cell arrays are sized for the smallest cell edge the tuner may choose.
+int max_cells(const ProblemWs& w) { return ceil_div(w.p.nx, kCellMin) * ceil_div(w.p.ny, kCellMin); }
+
 void plan_sizes(ProblemWs& w) {
   const letkf_problem& p = w.p;
   w.npts = p.nx * p.ny;
   w.kp = pow2_at_least16(p.k);
   w.nb = n_upper_blocks(w.kp);
-  w.ncx = ceil_div(p.nx, kCell);
-  w.ncy = ceil_div(p.ny, kCell);
-  w.ncells = w.ncx * w.ncy;
+  set_cell(w, kCell);
   w.nobs_alloc = p.n_obs_max > 0 ? p.n_obs_max : 1;
 }
 
@@ -171,7 +183,7 @@ uint64_t ws_bytes(const ProblemWs& w, bool cycle) {
   const uint64_t state = (uint64_t)w.npts * 9 * w.p.k * sizeof(double);
   uint64_t b = state * (cycle ? 2 : 1);
   b += no * 5 * sizeof(int) + no * w.kp * ystride + no * 2 * sizeof(double);
-  b += (uint64_t)(3 * w.ncells + 1) * sizeof(int);
+  b += (uint64_t)(3 * max_cells(w) + 1) * sizeof(int);
   return b;
 }
 
@@ -181,7 +193,7 @@ GramArgs gram_desc(const ProblemWs& w) {
   ga.nx = p.nx;
   ga.ny = p.ny;
   ga.k = p.k;
-  ga.cb = kCell;
+  ga.cb = w.cell;
   ga.ncx = w.ncx;
   ga.ncy = w.ncy;
   ga.loc = p.loc;
@@ -231,7 +243,7 @@ ObsArgs obs_args(const ProblemWs& w, const letkf_io& io, int* status) {
   oa.kq = w.kp;
   oa.npts = w.npts;
   oa.n_obs = io.n_obs;
-  oa.cb = kCell;
+  oa.cb = w.cell;
   oa.ncx = w.ncx;
   oa.ncy = w.ncy;
   oa.ncells = w.ncells;
@@ -258,8 +270,9 @@ ObsArgs obs_args(const ProblemWs& w, const letkf_io& io, int* status) {
   return oa;
 }
 
-hipError_t launch_gram(const BatchMap& bm, int kp, int prec, hipStream_t s) {
-  return prec == LETKF_PREC_FP64 ? launch_gram_f64(bm, kp, s) : launch_gram_lp(bm, kp, prec, s);
+hipError_t launch_gram(const BatchMap& bm, int kp, int prec, bool persistent, hipStream_t s) {
+  return prec == LETKF_PREC_FP64 ? launch_gram_f64(bm, kp, persistent, s)
+                                 : launch_gram_lp(bm, kp, prec, persistent, s);
 }
 
 hipError_t launch_evd(const BatchMap& bm, int kp, hipStream_t s) {
@@ -301,10 +314,11 @@ int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* 
   bm.nprob = nprob;
   bm.C = pl->slab_C;
   bm.b = pl->slab_b;
+  bm.queue = pl->queue;
   for (int g0 = 0; g0 < total; g0 += slab) {
     bm.g0 = g0;
     bm.n = std::min(slab, total - g0);
-    if (launch_gram(bm, kp, prec, s) != hipSuccess) return LETKF_EDEVICE;
+    if (launch_gram(bm, kp, prec, pl->gram_persistent, s) != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
     if (launch_evd(bm, kp, s) != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
@@ -411,6 +425,36 @@ bool upload(const std::vector<T>& h, T* d) {
   return hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
 }
 
+// Kernel descriptors of every problem (and of each class's concatenation)
+// from the plan's current settings, into the plan's device tables.
+bool upload_descriptors(letkf_plan_s* pl) {
+  const int n_probs = (int)pl->probs.size();
+  std::vector<GramArgs> g_host(n_probs);
+  std::vector<EvdArgs> e_host(n_probs);
+  std::vector<int> pre_host(2 * (size_t)n_probs);
+  for (int i = 0; i < n_probs; ++i) {
+    g_host[i] = gram_desc(pl->probs[i]);
+    e_host[i] = evd_desc(pl->probs[i], pl->stat + 1);
+    pre_host[2 * i] = 0;
+    pre_host[2 * i + 1] = pl->probs[i].npts;
+  }
+  bool ok = upload(g_host, pl->g_one) && upload(e_host, pl->e_one) &&
+            upload(pre_host, pl->prefix_one);
+  for (auto& c : pl->classes) {
+    const size_t n = c.members.size();
+    std::vector<GramArgs> gc(n);
+    std::vector<EvdArgs> ec(n);
+    std::vector<int> pc(n + 1, 0);
+    for (size_t j = 0; j < n; ++j) {
+      gc[j] = g_host[c.members[j]];
+      ec[j] = e_host[c.members[j]];
+      pc[j + 1] = pc[j] + pl->probs[c.members[j]].npts;
+    }
+    ok = ok && upload(gc, c.g) && upload(ec, c.e) && upload(pc, c.prefix);
+  }
+  return ok;
+}
+
 }  // namespace
 
 extern "C" {
@@ -502,39 +546,20 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
       w.Ylp = q;
     }
     ok = ok && pl->alloc(&w.d, no) && pl->alloc(&w.rinv, no);
-    ok = ok && pl->alloc(&w.cell_count, w.ncells) && pl->alloc(&w.cell_start, w.ncells + 1) &&
-         pl->alloc(&w.cell_fill, w.ncells);
+    const int mc = max_cells(w);
+    ok = ok && pl->alloc(&w.cell_count, mc) && pl->alloc(&w.cell_start, mc + 1) &&
+         pl->alloc(&w.cell_fill, mc);
     if (cycle) ok = ok && pl->alloc(&w.bgk, (size_t)w.npts * 9 * k);
   }
   ok = ok && pl->alloc(&pl->slab_C, (size_t)c_doubles) && pl->alloc(&pl->slab_b, (size_t)b_doubles);
   // descriptors: one per problem, and one table per class
-  std::vector<GramArgs> g_host(n_probs);
-  std::vector<EvdArgs> e_host(n_probs);
-  std::vector<int> pre_host(2 * (size_t)n_probs);
-  for (int i = 0; ok && i < n_probs; ++i) {
-    g_host[i] = gram_desc(pl->probs[i]);
-    e_host[i] = evd_desc(pl->probs[i], pl->stat + 1);
-    pre_host[2 * i] = 0;
-    pre_host[2 * i + 1] = pl->probs[i].npts;
-  }
   ok = ok && pl->alloc(&pl->g_one, n_probs) && pl->alloc(&pl->e_one, n_probs) &&
-       pl->alloc(&pl->prefix_one, 2 * (size_t)n_probs);
-  ok = ok && upload(g_host, pl->g_one) && upload(e_host, pl->e_one) &&
-       upload(pre_host, pl->prefix_one);
+       pl->alloc(&pl->prefix_one, 2 * (size_t)n_probs) && pl->alloc(&pl->queue, kQueueSlots);
   for (auto& c : pl->classes) {
-    if (!ok) break;
     const size_t n = c.members.size();
-    std::vector<GramArgs> gc(n);
-    std::vector<EvdArgs> ec(n);
-    std::vector<int> pc(n + 1, 0);
-    for (size_t j = 0; j < n; ++j) {
-      gc[j] = g_host[c.members[j]];
-      ec[j] = e_host[c.members[j]];
-      pc[j + 1] = pc[j] + pl->probs[c.members[j]].npts;
-    }
     ok = ok && pl->alloc(&c.g, n) && pl->alloc(&c.e, n) && pl->alloc(&c.prefix, n + 1);
-    ok = ok && upload(gc, c.g) && upload(ec, c.e) && upload(pc, c.prefix);
   }
+  ok = ok && upload_descriptors(pl);
   if (ok && opt && (opt->flags & LETKF_FLAG_PHASE_TIMING)) {
     int max_slabs = 0;
     for (auto& c : pl->classes) max_slabs += ceil_div(c.total, c.slab);
@@ -608,6 +633,98 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
   if (rc == LETKF_OK)
     rc = enqueue(plan, ios.data(), src.data(), n_io, covers_all_once(plan, ios.data(), n_io), s);
   plan->last_stream = s;
+  plan->busy.store(0);
+  return rc;
+}
+
+int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream,
+               letkf_tuning* out) {
+  if (!plan || !io || n_io < 1) return LETKF_EINVAL;
+  for (int i = 0; i < n_io; ++i) {
+    const int rc = check_io(plan, io[i]);
+    if (rc != LETKF_OK) return rc;
+  }
+  int expect = 0;
+  if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // the kernel descriptors are rewritten below: earlier calls must be done
+  if (hipStreamSynchronize(plan->last_stream) != hipSuccess) {
+    plan->busy.store(0);
+    return LETKF_EDEVICE;
+  }
+  std::vector<const double*> src(n_io);
+  for (int i = 0; i < n_io; ++i) src[i] = io[i].xb;
+  const bool batched = covers_all_once(plan, io, n_io);
+  const bool saved_timing = plan->timing;
+  plan->timing = false;                          // tuning calls stay out of the phase record
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess ? LETKF_OK
+                                                                                 : LETKF_EDEVICE;
+  constexpr int kCells[3] = {4, 8, 16};
+  constexpr int kReps = 2;
+  double best_ms = 0.0;
+  int best_cell = kCell;
+  bool best_persist = false;
+  bool have = false;
+  for (int ci = 0; ci < 3 && rc == LETKF_OK; ++ci) {
+    for (int pi = 0; pi < 2 && rc == LETKF_OK; ++pi) {
+      for (auto& w : plan->probs) set_cell(w, kCells[ci]);
+      plan->gram_persistent = pi == 1;
+      if (!upload_descriptors(plan)) {
+        rc = LETKF_EDEVICE;
+        break;
+      }
+      rc = enqueue(plan, io, src.data(), n_io, batched, s);          // warm-up
+      if (rc == LETKF_OK && hipEventRecord(e0, s) != hipSuccess) rc = LETKF_EDEVICE;
+      for (int r = 0; r < kReps && rc == LETKF_OK; ++r) rc = enqueue(plan, io, src.data(), n_io, batched, s);
+      float ms = 0.f;
+      if (rc == LETKF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = LETKF_EDEVICE;
+      if (rc == LETKF_OK && (!have || ms / kReps < best_ms)) {
+        have = true;
+        best_ms = ms / kReps;
+        best_cell = kCells[ci];
+        best_persist = pi == 1;
+      }
+    }
+  }
+  for (auto& w : plan->probs) set_cell(w, best_cell);
+  plan->gram_persistent = best_persist;
+  if (!upload_descriptors(plan) && rc == LETKF_OK) rc = LETKF_EDEVICE;
+  if (rc == LETKF_OK) {
+    // leave the outputs as one plain analysis with the chosen settings would
+    rc = enqueue(plan, io, src.data(), n_io, batched, s);
+    if (rc == LETKF_OK && hipStreamSynchronize(s) != hipSuccess) rc = LETKF_EDEVICE;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  plan->timing = saved_timing;
+  plan->last_stream = s;
+  plan->busy.store(0);
+  if (rc == LETKF_OK && out) {
+    out->cell = best_cell;
+    out->gram_persistent = best_persist ? 1 : 0;
+    out->ms_per_call = best_ms;
+  }
+  return rc;
+}
+
+int letkf_set_tuning(letkf_plan_t plan, const letkf_tuning* t) {
+  if (!plan || !t) return LETKF_EINVAL;
+  if (t->cell != 4 && t->cell != 8 && t->cell != 16) return LETKF_EINVAL;
+  if (t->gram_persistent != 0 && t->gram_persistent != 1) return LETKF_EINVAL;
+  int expect = 0;
+  if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
+  DeviceGuard guard(plan->device);
+  int rc = hipStreamSynchronize(plan->last_stream) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+  if (rc == LETKF_OK) {
+    for (auto& w : plan->probs) set_cell(w, t->cell);
+    plan->gram_persistent = t->gram_persistent == 1;
+    if (!upload_descriptors(plan)) rc = LETKF_EDEVICE;
+  }
   plan->busy.store(0);
   return rc;
 }

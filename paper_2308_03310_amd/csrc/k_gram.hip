@@ -106,25 +106,20 @@ __device__ __forceinline__ void gram_step(GramAcc<KQ>& acc, const GramArgs& g, c
   }
 }
 
+// The localized Gram matrix and right-hand side of slab-local point pl, by
+// one wavefront; ring_s / ring_w are its LDS ring of local observations.
 template <int KQ>
-__global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
+__device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* ring_s,
+                                               double* ring_w) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
-  __shared__ int s_ring[4][128];
-  __shared__ double w_ring[4][128];
-  const int wid = threadIdx.x >> 6, lane = lane_id();
-  const int nblocks = gridDim.x;
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int pl = lb * 4 + wid;            // slab-local point
-  if (pl >= bm.n) return;
+  const int lane = lane_id();
   const int gidx = bm.g0 + pl;
   const int prob = find_problem(bm.prefix, bm.nprob, gidx);
   const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];  // point within its problem
   const int x = pt % g.nx, y = pt / g.nx;
-  int* ring_s = s_ring[wid];
-  double* ring_w = w_ring[wid];
 
   GramAcc<KQ> acc;
 #pragma unroll
@@ -203,16 +198,43 @@ __global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
   }
 }
 
-hipError_t launch_gram_f64(const BatchMap& a, int kp, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  const dim3 grid(ceil_div(a.n, 4)), block(256);
-  switch (kp) {
-    case 16: hipLaunchKernelGGL(k_gram_f64<16>, grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_gram_f64<32>, grid, block, 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_gram_f64<64>, grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
+// Grid form: one wavefront per point, four points per block, blocks remapped
+// so that neighbouring points (which share observations) stay on one XCD.
+// Persistent form: a device-filling grid whose wavefronts take points from
+// per-XCD work queues over contiguous eighths of the slab and, once their
+// own eighth is done, from the others' (load balance when the local
+// observation counts differ widely between points).
+template <int KQ, bool PERSIST>
+__global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
+  __shared__ int s_ring[4][128];
+  __shared__ double w_ring[4][128];
+  const int wid = threadIdx.x >> 6;
+  if constexpr (!PERSIST) {
+    const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
+    if (pl < bm.n) gram_f64_point<KQ>(bm, pl, s_ring[wid], w_ring[wid]);
+  } else {
+    for_each_queued_point(bm, [&](int pl) { gram_f64_point<KQ>(bm, pl, s_ring[wid], w_ring[wid]); });
   }
-  return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const BatchMap& a, int kp, bool persistent, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (persistent && launch_fill_i32(a.queue, kQueueSlots, 0, s) != hipSuccess)
+    return hipErrorLaunchFailure;
+  const dim3 grid(persistent ? persistent_blocks(a.n, 4) : ceil_div(a.n, 4)), block(256);
+#define LETKF_GRAM_F64(KP_)                                                                   \
+  if (kp == KP_) {                                                                           \
+    if (persistent)                                                                          \
+      hipLaunchKernelGGL((k_gram_f64<KP_, true>), grid, block, 0, s, a);                      \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_gram_f64<KP_, false>), grid, block, 0, s, a);                     \
+    return hipGetLastError();                                                                \
+  }
+  LETKF_GRAM_F64(16)
+  LETKF_GRAM_F64(32)
+  LETKF_GRAM_F64(64)
+#undef LETKF_GRAM_F64
+  return hipErrorInvalidValue;
 }
 
 }  // namespace letkf

@@ -150,24 +150,18 @@ __device__ __forceinline__ void gram_step_bf16(GramAccLp<KQ, 2>& acc, const Gram
 }
 
 template <int KQ, int PREC>
-__global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
+__device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* ring_s,
+                                              double* ring_w) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   constexpr int STEP = PREC == 1 ? 4 : 16;
-  __shared__ int s_ring[4][128];
-  __shared__ double w_ring[4][128];
-  const int wid = threadIdx.x >> 6, lane = lane_id();
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int pl = lb * 4 + wid;            // slab-local point
-  if (pl >= bm.n) return;
+  const int lane = lane_id();
   const int gidx = bm.g0 + pl;
   const int prob = find_problem(bm.prefix, bm.nprob, gidx);
   const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];
   const int x = pt % g.nx, y = pt / g.nx;
-  int* ring_s = s_ring[wid];
-  double* ring_w = w_ring[wid];
 
   GramAccLp<KQ, PREC> acc;
 #pragma unroll
@@ -244,11 +238,33 @@ __global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
   }
 }
 
-hipError_t launch_gram_lp(const BatchMap& a, int kp, int prec, hipStream_t s) {
+// Grid and persistent forms, as for k_gram_f64.
+template <int KQ, int PREC, bool PERSIST>
+__global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
+  __shared__ int s_ring[4][128];
+  __shared__ double w_ring[4][128];
+  const int wid = threadIdx.x >> 6;
+  if constexpr (!PERSIST) {
+    const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
+    if (pl < bm.n) gram_lp_point<KQ, PREC>(bm, pl, s_ring[wid], w_ring[wid]);
+  } else {
+    for_each_queued_point(bm, [&](int pl) { gram_lp_point<KQ, PREC>(bm, pl, s_ring[wid], w_ring[wid]); });
+  }
+}
+
+hipError_t launch_gram_lp(const BatchMap& a, int kp, int prec, bool persistent, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const dim3 grid(ceil_div(a.n, 4)), block(256);
-#define LETKF_GRAM_LP(KP_, PR_) \
-  if (kp == KP_ && prec == PR_) { hipLaunchKernelGGL((k_gram_lp<KP_, PR_>), grid, block, 0, s, a); return hipGetLastError(); }
+  if (persistent && launch_fill_i32(a.queue, kQueueSlots, 0, s) != hipSuccess)
+    return hipErrorLaunchFailure;
+  const dim3 grid(persistent ? persistent_blocks(a.n, 4) : ceil_div(a.n, 4)), block(256);
+#define LETKF_GRAM_LP(KP_, PR_)                                                               \
+  if (kp == KP_ && prec == PR_) {                                                            \
+    if (persistent)                                                                          \
+      hipLaunchKernelGGL((k_gram_lp<KP_, PR_, true>), grid, block, 0, s, a);                  \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_gram_lp<KP_, PR_, false>), grid, block, 0, s, a);                 \
+    return hipGetLastError();                                                                \
+  }
   LETKF_GRAM_LP(16, 1)
   LETKF_GRAM_LP(32, 1)
   LETKF_GRAM_LP(64, 1)

@@ -89,8 +89,39 @@ struct BatchMap {
   int g0, n;           // slab: global points [g0, g0 + n)
   double* C;           // [n][NB][256]
   double* b;           // [n][KP]
+  int* queue;          // [kQueueSlots] work counters of the persistent launches
   EvdArgs e_inline;
 };
+
+// Work queues of a persistent launch: one counter per XCD (blocks are
+// dispatched round-robin over the 8 XCDs), each over a contiguous eighth of
+// the slab; a wavefront that drains its own moves on to the next XCD's.
+constexpr int kQueueSlots = 8;
+constexpr int kPersistentBlocksPerCu = 8;
+constexpr int kDeviceCus = 256;
+
+inline int persistent_blocks(int n, int per_block) {
+  const int full = kDeviceCus * kPersistentBlocksPerCu;
+  const int need = (n + per_block - 1) / per_block;
+  return need < full ? need : full;
+}
+
+template <class F>
+__device__ __forceinline__ void for_each_queued_point(const BatchMap& bm, F&& f) {
+  const int home = blockIdx.x & (kQueueSlots - 1);
+  for (int qi = 0; qi < kQueueSlots; ++qi) {
+    const int q = (home + qi) & (kQueueSlots - 1);
+    const int lo = (int)((int64_t)bm.n * q / kQueueSlots);
+    const int hi = (int)((int64_t)bm.n * (q + 1) / kQueueSlots);
+    for (;;) {
+      int off = 0;
+      if (__lane_id() == 0) off = atomicAdd(bm.queue + q, 1);
+      off = __builtin_amdgcn_readfirstlane(off);
+      if (lo + off >= hi) break;             // wave-uniform exit
+      f(lo + off);
+    }
+  }
+}
 
 __device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gidx) {
   int lo = 0, hi = nprob;
@@ -109,8 +140,8 @@ hipError_t launch_transpose_in(const double* xb, double* xt, int k, int npts, co
 hipError_t launch_transpose_out(const double* xt, double* xa, int k, int npts,
                                 const int* abort_flag, hipStream_t s);
 hipError_t launch_obs_operator(const ObsArgs& a, hipStream_t s);
-hipError_t launch_gram_f64(const BatchMap& bm, int kp, hipStream_t s);
-hipError_t launch_gram_lp(const BatchMap& bm, int kp, int prec, hipStream_t s);
+hipError_t launch_gram_f64(const BatchMap& bm, int kp, bool persistent, hipStream_t s);
+hipError_t launch_gram_lp(const BatchMap& bm, int kp, int prec, bool persistent, hipStream_t s);
 template <int KP>
 hipError_t launch_evd_kp(const BatchMap& bm, hipStream_t s);
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,

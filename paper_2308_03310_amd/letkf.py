@@ -47,6 +47,11 @@ class letkf_io(ctypes.Structure):
                 ("obs_var", ctypes.c_void_p)]
 
 
+class letkf_tuning(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32), ("gram_persistent", ctypes.c_int32),
+                ("ms_per_call", ctypes.c_double)]
+
+
 class letkf_cycle_io(ctypes.Structure):
     _fields_ = [("io", letkf_io), ("n_steps", ctypes.c_int32), ("force_kx", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("force_amp", ctypes.c_double)]
@@ -84,6 +89,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.letkf_phase_times.restype = ctypes.c_int
     lib.letkf_eigh_batched.argtypes = [dp, i32, i32, dp, dp, dp, vp]
     lib.letkf_eigh_batched.restype = ctypes.c_int
+    lib.letkf_tune.argtypes = [vp, ctypes.POINTER(letkf_io), i32, vp, ctypes.POINTER(letkf_tuning)]
+    lib.letkf_tune.restype = ctypes.c_int
+    lib.letkf_set_tuning.argtypes = [vp, ctypes.POINTER(letkf_tuning)]
+    lib.letkf_set_tuning.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -218,3 +227,18 @@ def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
         _ptr(a, torch.float64), batch, k, _ptr(lam, torch.float64), _ptr(vec, torch.float64),
         _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
         "letkf_eigh_batched")
+
+
+def letkf_tune(plan: int, ios: Iterable[letkf_io], stream=None) -> dict:
+    """Autotune the plan's launch settings on these analyses; returns the setting kept."""
+    ios = list(ios)
+    arr = (letkf_io * len(ios))(*ios)
+    t = letkf_tuning()
+    _check(load_library().letkf_tune(plan, arr, len(ios), _stream(stream), ctypes.byref(t)),
+           "letkf_tune")
+    return {"cell": t.cell, "gram_persistent": t.gram_persistent, "ms_per_call": t.ms_per_call}
+
+
+def letkf_set_tuning(plan: int, cell: int, gram_persistent: int) -> int:
+    t = letkf_tuning(int(cell), int(gram_persistent), 0.0)
+    return _check(load_library().letkf_set_tuning(plan, ctypes.byref(t)), "letkf_set_tuning")

@@ -49,6 +49,11 @@ class Workload:
     infl: float          # multiplicative inflation rho
     seed: int
     kinds: tuple = (OBS_U, OBS_V)
+    # random observation mask instead of the stride lattice: Bernoulli(density)
+    # per point, minus n_gaps discs with radii in gap_radius (clustered gaps)
+    density: float = 0.0
+    n_gaps: int = 0
+    gap_radius: tuple = (8, 32)
 
 
 # The five shapes the method is exercised on (see the bench / tests).
@@ -119,7 +124,12 @@ def make_problem(wl: Workload, seed: Optional[int] = None, dtype=np.float64) -> 
         sp = 0.01 / np.sqrt(0.5 * np.mean(up * up + vp * vp))
         rho = 1.0 + 1e-3 * rng.standard_normal((ny, nx))
         xb[m] = equilibrium(rho, ut + sp * up, vt + sp * vp)
-    iy, ix = np.meshgrid(np.arange(0, ny, wl.stride), np.arange(0, nx, wl.stride), indexing="ij")
+    if wl.density > 0.0:
+        mask = obs_mask(rng, nx, ny, wl.density, wl.n_gaps, wl.gap_radius)
+        iy, ix = np.nonzero(mask)
+    else:
+        iy, ix = np.meshgrid(np.arange(0, ny, wl.stride), np.arange(0, nx, wl.stride),
+                             indexing="ij")
     iy = iy.ravel().astype(np.int32)
     ix = ix.ravel().astype(np.int32)
     n_pts = ix.size
@@ -133,6 +143,41 @@ def make_problem(wl: Workload, seed: Optional[int] = None, dtype=np.float64) -> 
     var = np.full(val.shape, wl.sigma ** 2)
     return Problem(wl, xb, obs_ix.astype(np.int32), obs_iy.astype(np.int32),
                    obs_kind.astype(np.int32), val.astype(np.float64), var, ut, vt)
+
+
+def obs_mask(rng: np.random.Generator, nx: int, ny: int, density: float, n_gaps: int,
+             gap_radius=(8, 32)) -> np.ndarray:
+    """[ny, nx] bool: Bernoulli(density) observation sites with n_gaps
+    periodic discs (radius uniform in gap_radius, capped at a quarter of the
+    box) emptied -- observation gaps clustered in space."""
+    mask = rng.random((ny, nx)) < density
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for _ in range(n_gaps):
+        r = min(rng.uniform(*gap_radius), min(nx, ny) / 4)
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        dx = np.abs(xx - cx)
+        dx = np.minimum(dx, nx - dx)
+        dy = np.abs(yy - cy)
+        dy = np.minimum(dy, ny - dy)
+        mask &= dx * dx + dy * dy > r * r
+    return mask
+
+
+def batching_workloads(n: int, seed: int = 3, grids=(64, 128, 256, 512), ks=(16, 32, 64)):
+    """The mixed batch: n independent problems with lattice sizes drawn from
+    grids, k from ks, L ~ U[4, 16], sigma ~ U[0.002, 0.01], rho = 1.1, random
+    observation masks of density U[0.05, 0.5] with 1-6 clustered gaps of
+    radius 8-32 (so local observation counts range from 0 to several
+    hundred).  Every draw comes from one seeded generator."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        g = int(rng.choice(grids))
+        out.append(Workload(f"batch{seed}_{i}", g, g, int(rng.choice(ks)), 1,
+                            float(rng.uniform(0.002, 0.01)), float(rng.uniform(4.0, 16.0)), 1.1,
+                            int(rng.integers(1 << 30)), density=float(rng.uniform(0.05, 0.5)),
+                            n_gaps=int(rng.integers(1, 7))))
+    return out
 
 
 def _gather_truth(truth, kind, iy, ix):

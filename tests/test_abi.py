@@ -20,7 +20,8 @@ def lib():
 def test_exports_every_declared_function(lib):
     names = L.header_functions()
     assert {"letkf_plan", "letkf_analyze", "letkf_cycle", "letkf_status", "letkf_plan_destroy",
-            "letkf_strerror", "letkf_eigh_batched", "letkf_plan_workspace_bytes"} <= set(names)
+            "letkf_strerror", "letkf_eigh_batched", "letkf_plan_workspace_bytes", "letkf_tune",
+            "letkf_set_tuning"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
 
@@ -85,3 +86,9 @@ def test_valid_descriptor_without_gpu_is_edevice(lib):
     p = L.make_problem(**GOOD)
     rc, h = L.letkf_plan([p], raise_on_error=False)
     assert rc == L.LETKF_EDEVICE and h is None
+
+
+def test_tuning_calls_reject_bad_arguments(lib):
+    t = L.letkf_tuning(8, 0, 0.0)
+    assert lib.letkf_set_tuning(None, ctypes.byref(t)) == L.LETKF_EINVAL
+    assert lib.letkf_tune(None, None, 0, None, ctypes.byref(t)) == L.LETKF_EINVAL
