@@ -160,6 +160,65 @@ def precision_form(L, torch, steps: int):
     return res
 
 
+def batching_form(L, torch, n: int, grids):
+    """The batching form: n independent problems drawn by the mixed-batch
+    recipe (lattice sizes from grids, k from {16, 32, 64}, random masks with
+    clustered gaps), timed as one batched call with the default launch
+    settings, after letkf_tune, and as one call per problem."""
+    dev = torch.device("cuda:0")
+    wls = synth.batching_workloads(n, seed=3, grids=grids)
+    probs, ios, keep = [], [], []
+    n_obs = []
+    for i, wl in enumerate(wls):
+        p = synth.make_problem(wl)
+        obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                    (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
+        xb = torch.from_numpy(p.xb).to(dev)
+        xa = torch.empty_like(xb)
+        keep.append((xb, xa, obs))
+        probs.append(L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl))
+        ios.append(L.make_io(i, xb, xa, obs))
+        n_obs.append(len(p.obs_ix))
+        del p
+    points = sum(w.nx * w.ny for w in wls)
+    plan = L.letkf_plan(probs)
+    stream = torch.cuda.current_stream()
+
+    def timed(calls, reps=3):
+        for c in calls:                                   # warm-up
+            L.letkf_analyze(plan, c, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            for c in calls:
+                L.letkf_analyze(plan, c, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    try:
+        ms_default = timed([ios])
+        ms_single = timed([[io] for io in ios])
+        tune = L.letkf_tune(plan, ios, stream)
+        ms_tuned = timed([ios])
+        st = L.letkf_status(plan, sync=True)
+        if st != L.LETKF_OK:
+            raise SystemExit(f"batching form: {L.letkf_strerror(st)}")
+    finally:
+        L.letkf_plan_destroy(plan)
+        del keep
+        torch.cuda.empty_cache()
+    rate = lambda ms: round(points / (ms / 1e3), 1)
+    return {"problems": n, "grids": list(grids), "grid_points": points,
+            "obs_per_problem": [min(n_obs), max(n_obs)],
+            "batched_default": {"ms": round(ms_default, 3), "value": rate(ms_default)},
+            "batched_tuned": {"ms": round(ms_tuned, 3), "value": rate(ms_tuned), "setting": tune},
+            "one_call_per_problem": {"ms": round(ms_single, 3), "value": rate(ms_single)},
+            "unit": "grid-point analyses/s"}
+
+
 def cpu_baseline(wl, p, seconds: float):
     """The oracle, as it is, on a bounded sample of the workload's grid points."""
     from threadpoolctl import threadpool_limits
@@ -195,6 +254,10 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "timed loop (the known-size reference for HBM byte counters)")
+    ap.add_argument("--batching-problems", type=int, default=64,
+                    help="problems of the mixed-batch measurement (0 to skip)")
+    ap.add_argument("--batching-grids", default="64,128,256",
+                    help="lattice edges the mixed batch draws from")
     ap.add_argument("--precision-steps", type=int, default=2,
                     help="timed analyses per precision form on the 1024^2, k = 64 workload "
                          "(0 to skip)")
@@ -305,10 +368,14 @@ def main():
             out["serving"]["cycle"] = "50 BGK steps (tau 0.52, Kolmogorov forcing 1e-5) + analysis"
         finally:
             srv.close()
-    if args.precision_steps > 0:
+    if args.precision_steps > 0 or args.batching_problems > 0:
         del xb, xa, obs
         torch.cuda.empty_cache()
+    if args.precision_steps > 0:
         out["precision_form"] = precision_form(L, torch, args.precision_steps)
+    if args.batching_problems > 0:
+        out["batching_form"] = batching_form(L, torch, args.batching_problems,
+                                             tuple(int(g) for g in args.batching_grids.split(",")))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

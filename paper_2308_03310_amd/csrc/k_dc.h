@@ -51,7 +51,7 @@ struct DcLds {
 };
 
 constexpr double kDcEps = 0x1p-52;
-constexpr int kSecularMaxIts = 48;
+constexpr int kSecularMaxIts = 64;   // room for a full bisection to 2 ulps
 
 // The root of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  (p1 < p2, B1, B2 >= 0: the
 // function rises from -inf to +inf between the poles) that lies in the
@@ -100,23 +100,28 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   double s2 = 0.0;
 #pragma unroll 8
   for (int j = 0; j < S; ++j) s2 = fma(w[j], w[j], s2);
-  // probe point: the interval midpoint (last root: halfway to d + rho |w|^2)
-  const double half = last ? 0.5 * rho * s2 : 0.5 * (di1 - di);
-  const double lm = di + half;
+  // probe point: the interval midpoint (last root: halfway to d + rho |w|^2),
+  // evaluated in coordinates shifted to d_i (d_j - d_i is exact for the
+  // nearby poles, d_j - (d_i + half) would not be when the gap is tiny)
+  const double gap = last ? rho * s2 : di1 - di;
+  const double half = 0.5 * gap;
   double fm = irho, ti = 0.0, ti1 = 0.0;
 #pragma unroll 8
   for (int j = 0; j < S; ++j) {
-    const double t = w[j] * w[j] * frcp(d[j] - lm);
+    const double t = w[j] * w[j] * frcp((d[j] - di) - half);
     fm += t;
     ti = j == i ? t : ti;
     ti1 = j == i + 1 ? t : ti1;
   }
+  // origin: the pole nearer the root (the sign of f at the midpoint); the
+  // bracket is that half of the interval (its far end excludes the other
+  // pole, next to which the model's second root can round into the interval)
   int org;
   double lo, hi;
   if (last) {
     org = i;
     lo = 0.0;
-    hi = rho * s2 * (1.0 + 8.0 * kDcEps);
+    hi = gap * (1.0 + 8.0 * kDcEps);
   } else if (fm >= 0.0) {
     org = i;
     lo = 0.0;
@@ -134,10 +139,11 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   // start: the nearest poles exact, the other terms frozen at the probe point
   double tau;
   {
+    const double tm = fm >= 0.0 || last ? half : -half;   // the probe, shifted to the origin
     const double rest = fm - ti - ti1;
     const double t0 = last ? (rest > 0.0 ? pi + wi2 / rest : __builtin_nan(""))
                            : two_pole_root(rest, wi2, wi12, pi, pi1, lo, hi);
-    tau = (t0 > lo && t0 < hi) ? t0 : 0.5 * (lo + hi);
+    tau = (t0 > lo && t0 < hi) ? t0 : tm;
   }
   // Iteration on a two-pole model: the terms of the two poles nearest the
   // root (e1 < e2) are kept exact, the far terms below e1 and above e2 are
