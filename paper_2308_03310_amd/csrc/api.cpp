@@ -228,6 +228,9 @@ EvdArgs evd_desc(const ProblemWs& w, int* status) {
   ea.npts = w.npts;
   ea.alpha = (double)(p.k - 1) / p.infl;
   ea.sqrt_km1 = std::sqrt((double)(p.k - 1));
+  // Q carries the rounding of its contractions: FP64 unit roundoff for the
+  // FP64 form, FP32's for the FP32 and BF16 forms (FP32 accumulation).
+  ea.defl_eps = p.precision == LETKF_PREC_FP64 ? 0x1p-52 : 0x1p-24;
   ea.xt = w.xt;
   ea.abort_flag = w.abort_flag;
   ea.status = status;
@@ -807,6 +810,7 @@ int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, d
   ea.mode = 1;
   ea.k = k;
   ea.npts = batch;
+  ea.defl_eps = 0x1p-52;
   ea.A = a;
   ea.lam = lam;
   ea.vec = vec;

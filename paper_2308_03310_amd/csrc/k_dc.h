@@ -248,7 +248,7 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
 // scratch for the merge matrices (KP * (KP + 1) doubles).
 template <int KP, int S>
 __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const double* e_orig,
-                                         double* W, int jj, bool& ok) {
+                                         double* W, int jj, double deps, bool& ok) {
   constexpr int H = S / 2;
   constexpr int WS = S + 1;                  // row stride of a block's merge matrix
   const int t = jj & (S - 1);
@@ -285,7 +285,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   L.ds[a + rank] = D;
   L.ws[a + rank] = w;
   L.pm[a + rank] = t;
-  const double tol = 8.0 * kDcEps * fmax(group_max<S>(fabs(D)), rho);
+  const double tol = 8.0 * deps * fmax(group_max<S>(fabs(D)), rho);
   wave_lds_sync();
   // deflation: negligible weights (lane-parallel), then pairs of close poles
   // (a sequential scan by one lane over the sorted order)
@@ -433,27 +433,29 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
 
 template <int KP, int S>
 __device__ __forceinline__ void dc_levels(double (&qs)[KP], DcLds<KP>& L, const double* e_orig,
-                                          double* W, int jj, bool& ok) {
+                                          double* W, int jj, double deps, bool& ok) {
   if constexpr (S <= KP) {
-    dc_merge<KP, S>(qs, L, e_orig, W, jj, ok);
-    dc_levels<KP, 2 * S>(qs, L, e_orig, W, jj, ok);
+    dc_merge<KP, S>(qs, L, e_orig, W, jj, deps, ok);
+    dc_levels<KP, 2 * S>(qs, L, e_orig, W, jj, deps, ok);
   }
 }
 
 // Eigen-decomposition of the tridiagonal (d, e) (LDS, KP entries each; e
-// is not modified).  On return L.lam[jj] is the eigenvalue of column jj and
+// is not modified).  Deflation tolerance 8 deps max(|D|, rho) per merge, with
+// deps the unit roundoff of the arithmetic that produced the matrix.  On
+// return L.lam[jj] is the eigenvalue of column jj and
 // qs[] is row jj of the eigenvector matrix.  Returns false if a secular root
 // ran out of iterations.
 template <int KP>
 __device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], DcLds<KP>& L, const double* d,
-                                               const double* e, double* W, int jj) {
+                                               const double* e, double* W, int jj, double deps) {
   const double el = jj > 0 ? e[jj - 1] : 0.0;
   L.lam[jj] = d[jj] - el - e[jj];            // leaves after tearing every coupling
 #pragma unroll
   for (int c = 0; c < KP; ++c) qs[c] = c == 0 ? 1.0 : 0.0;
   wave_lds_sync();
   bool ok = true;
-  dc_levels<KP, 2>(qs, L, e, W, jj, ok);
+  dc_levels<KP, 2>(qs, L, e, W, jj, deps, ok);
   return ok;
 }
 

@@ -66,6 +66,7 @@ struct EvdArgs {
   int pt0, npt;       // mode 0: points [pt0, pt0 + npt); mode 1: npt matrices
   double alpha;       // (k - 1) / rho
   double sqrt_km1;    // sqrt(k - 1)
+  double defl_eps;    // unit roundoff behind the deflation tolerance of the divide and conquer
   double* C;          // [npt][NB][256] upper 16x16 blocks of C (KP-padded); reused as
                       // scratch for the Householder reflectors once staged
   const double* b;    // [npt][KP]

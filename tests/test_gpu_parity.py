@@ -97,6 +97,74 @@ def test_eigh_batched_random(k):
         assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
 
 
+def _hard_matrices(k, family, n, rng):
+    """Batches of symmetric k x k matrices that stress a divide-and-conquer
+    eigensolver: nearly equal eigenvalues, Wilkinson's close pairs, weakly
+    coupled blocks, a graded spectrum, and the LETKF form with multiplicity."""
+    def orth(m):
+        q, r = np.linalg.qr(rng.standard_normal((m, m)))
+        return q * np.sign(np.diag(r))
+    out = np.empty((n, k, k))
+    for b in range(n):
+        if family == "clusters":          # clusters of 2-4 eigenvalues 1e-10 apart (relative)
+            lam = []
+            while len(lam) < k:
+                c = rng.uniform(1.0, 100.0)
+                lam += [c * (1.0 + 1e-10 * j) for j in range(rng.integers(2, 5))]
+            lam = np.array(lam[:k])
+            Q = orth(k)
+            out[b] = (Q * lam) @ Q.T
+        elif family == "wilkinson":       # W+: d_i = |m - i|, e = 1 (pairs agreeing to many digits)
+            m = (k - 1) / 2.0
+            out[b] = np.diag(np.abs(m - np.arange(k))) + np.diag(np.ones(k - 1), 1) + \
+                np.diag(np.ones(k - 1), -1)
+            if b % 2:
+                P = np.eye(k)[rng.permutation(k)]
+                out[b] = P @ out[b] @ P.T
+        elif family == "glued":           # blocks of 8 coupled by 1e-14
+            A = np.zeros((k, k))
+            for a0 in range(0, k, 8):
+                a1 = min(a0 + 8, k)
+                B = rng.standard_normal((a1 - a0, a1 - a0))
+                A[a0:a1, a0:a1] = B + B.T + 10.0 * np.eye(a1 - a0)
+                if a0 > 0:
+                    A[a0 - 1, a0] = A[a0, a0 - 1] = 1e-14
+            out[b] = A
+        elif family == "graded":          # eigenvalues from 1e-6 to 1e6
+            Q = orth(k)
+            out[b] = (Q * np.logspace(-6, 6, k)) @ Q.T
+        else:                             # letkf: alpha I + rank-r PSD, r < k
+            r = int(rng.integers(1, k))
+            Y = rng.standard_normal((r, k)) * np.sqrt(rng.uniform(0.1, 1e4, r))[:, None]
+            Y -= Y.mean(axis=1, keepdims=True)
+            out[b] = Y.T @ Y + (k - 1) / 1.1 * np.eye(k)
+    return 0.5 * (out + out.transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("family", ["clusters", "wilkinson", "glued", "graded", "letkf"])
+@pytest.mark.parametrize("k", [16, 21, 33, 64])
+def test_eigh_batched_hard_families(k, family):
+    import torch
+    n = 96
+    say(f"eigh_batched {family} k={k} batch={n}")
+    rng = np.random.default_rng(1000 + k)
+    A = _hard_matrices(k, family, n, rng)
+    lam = torch.empty(n, k, dtype=torch.float64, device="cuda")
+    vec = torch.empty(n, k, k, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L.letkf_eigh_batched(torch.from_numpy(A).cuda(), lam, vec, st)
+    torch.cuda.synchronize()
+    lam, vec = lam.cpu().numpy(), vec.cpu().numpy()
+    assert int(st.cpu()[0]) == 0
+    for i in range(n):
+        nrm = np.linalg.norm(A[i])
+        np.testing.assert_allclose(np.sort(lam[i]), np.linalg.eigvalsh(A[i]), rtol=0,
+                                   atol=1e-13 * nrm)
+        V = vec[i]
+        assert np.linalg.norm(V @ np.diag(lam[i]) @ V.T - A[i]) <= 1e-13 * nrm * k
+        assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
+
+
 # ------------------------------------------------------------ whole analyses
 def _oracle_full(p, L_len=None, infl=None, loc=orc.LOC_GAUSS, var=None):
     wl = p.wl
