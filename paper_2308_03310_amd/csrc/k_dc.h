@@ -26,28 +26,38 @@
 
 namespace letkf {
 
+// Per-matrix LDS of the merges.  Arrays that share storage are never live at
+// once: dt, zb and ws are dead once the keep list is built, before the
+// secular roots (rt, rd) and the recomputed weights (zh) are written.
 template <int KP>
 struct DcLds {
-  double lam[KP];   // eigenvalues of the current blocks, by position
-  double dt[KP];    // signed poles of a merge, block-local original order
-  double zb[KP];    // merge vector z
+  union {
+    double dt[KP];  // signed poles of a merge, block-local original order
+    double rt[KP];  // secular roots: offset tau from the origin pole
+  };
+  union {
+    double zb[KP];  // merge vector z
+    double rd[KP];  // secular roots: origin pole value
+  };
+  union {
+    double ws[KP];  // weights in sorted order
+    double zh[KP];  // recomputed weights zhat
+  };
   double ds[KP];    // poles sorted ascending
-  double ws[KP];    // weights in sorted order
-  double dk[KP];    // non-deflated poles (ascending)
-  double wk[KP];    // non-deflated weights
-  double rt[KP];    // secular roots: offset tau from the origin pole
-  double rd[KP];    // secular roots: origin pole value
-  double zh[KP];    // recomputed weights zhat
+  // non-deflated (pole, weight) pairs, ascending, per block of S slots: slots
+  // [2a, 2a + K) and again [2a + K, 2a + 2K), so that a walk over the K - 2
+  // poles away from a root, starting just above it and wrapping around,
+  // reads consecutive slots
+  alignas(16) double2 dw[2 * KP];
   double rc[KP];    // deflation rotations: cosine
   double rs[KP];    //                       sine
   int pm[KP];       // sorted position -> block-local original index
-  int kp[KP];       // non-deflated index -> sorted position
   int inv[KP];      // sorted position -> non-deflated index, -1 if deflated
   int rw[KP];       // non-deflated index -> block-local row of its eigenvector entry
-  int rp[KP];       // deflation rotations: first sorted position
-  int rj[KP];       //                       second sorted position
-  int nk[KP];       // per block (at its base): non-deflated count
-  int nr[KP];       //                          rotation count
+  // deflation rotations: first | second sorted position << 8; slot S - 1 of
+  // a block (never a rotation: a block of S poles has at most S - 2) holds
+  // the block's rotation count
+  int rot[KP];
 };
 
 constexpr double kDcEps = 0x1p-52;
@@ -81,25 +91,28 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(y, e, y);
 }
 
-// Pole value of an unused slot of the padded secular arrays (its weight is
-// zero, so every term it contributes is exactly zero).
-constexpr double kFarPole = 1e300;
-
-// Root i (0-based) of 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over the S slots
-// of d, w (LDS; slots >= K padded with d = kFarPole, w = 0), d ascending on
-// the first K slots, rho > 0, w_j != 0 for j < K.  Returns the origin pole
-// index with lambda = d[org] + tau_out; conv is cleared if the iteration
-// limit was hit.
-template <int S>
-__device__ __forceinline__ int secular_root(const double* d, const double* w, int K, int i,
-                                            double rho, double& tau_out, bool& conv) {
+// Root i (0-based) of f(lambda) = 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over
+// the K pairs dw[j] = (d_j, w_j) (LDS, d ascending, w_j != 0, rho > 0; slots
+// K .. 2K-1 repeat slots 0 .. K-1).  Returns the origin pole index with
+// lambda = d[org] + tau_out; conv is cleared if the iteration limit was hit.
+//
+// Every step keeps the terms of the two poles nearest the root (e1 < e2)
+// exact and replaces the sum F of the K - 2 others by c + s1/(P1 - t) +
+// s2/(P2 - t) on the same two poles, matching F and its first two
+// derivatives at the current iterate (Borges & Gragg 1993): cubic
+// convergence, and s1, s2 >= 0 for an interior root, so the model rises
+// monotonically between its poles.  For the root above the last pole both
+// model poles lie below it and the far terms are matched in value and slope
+// on P1 alone.  A bracket from the signs of f safeguards every step.
+__device__ __forceinline__ int secular_root(const double2* dw, int K, int i, double rho,
+                                            double& tau_out, bool& conv) {
   const double irho = 1.0 / rho;
   const bool last = i == K - 1;
-  const double di = d[i];
-  const double di1 = last ? di : d[i + 1];
+  const double di = dw[i].x;
+  const double di1 = last ? di : dw[i + 1].x;
   double s2 = 0.0;
 #pragma unroll 8
-  for (int j = 0; j < S; ++j) s2 = fma(w[j], w[j], s2);
+  for (int j = 0; j < K; ++j) s2 = fma(dw[j].y, dw[j].y, s2);
   // probe point: the interval midpoint (last root: halfway to d + rho |w|^2),
   // evaluated in coordinates shifted to d_i (d_j - d_i is exact for the
   // nearby poles, d_j - (d_i + half) would not be when the gap is tiny)
@@ -107,8 +120,9 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   const double half = 0.5 * gap;
   double fm = irho, ti = 0.0, ti1 = 0.0;
 #pragma unroll 8
-  for (int j = 0; j < S; ++j) {
-    const double t = w[j] * w[j] * frcp((d[j] - di) - half);
+  for (int j = 0; j < K; ++j) {
+    const double2 p = dw[j];
+    const double t = p.y * p.y * frcp((p.x - di) - half);
     fm += t;
     ti = j == i ? t : ti;
     ti1 = j == i + 1 ? t : ti1;
@@ -133,9 +147,9 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
   }
   const double dorg = last || fm >= 0.0 ? di : di1;
   const double pi = di - dorg, pi1 = di1 - dorg;
-  const double pm1 = i > 0 ? d[i - 1] - dorg : 0.0;
-  const double wi2 = w[i] * w[i];
-  const double wi12 = last ? 0.0 : w[i + 1] * w[i + 1];
+  const double pm1 = i > 0 ? dw[i - 1].x - dorg : 0.0;
+  const double wi2 = dw[i].y * dw[i].y;
+  const double wi12 = last ? 0.0 : dw[i + 1].y * dw[i + 1].y;
   // start: the nearest poles exact, the other terms frozen at the probe point
   double tau;
   {
@@ -145,56 +159,52 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
                            : two_pole_root(rest, wi2, wi12, pi, pi1, lo, hi);
     tau = (t0 > lo && t0 < hi) ? t0 : tm;
   }
-  // Iteration on a two-pole model: the terms of the two poles nearest the
-  // root (e1 < e2) are kept exact, the far terms below e1 and above e2 are
-  // each replaced by a constant plus a multiple of the nearer model pole that
-  // matches their value and slope at tau (so no dominant term is ever
-  // subtracted from a sum that contains it).
   const int e1 = last ? i - 1 : i;           // -1 when K == 1
   const int e2 = last ? i : i + 1;
   const double P1 = last ? pm1 : pi, P2 = last ? pi : pi1;
-  const double W1 = e1 >= 0 ? w[e1] * w[e1] : 0.0, W2 = w[e2] * w[e2];
+  const double W1 = e1 >= 0 ? dw[e1].y * dw[e1].y : 0.0, W2 = dw[e2].y * dw[e2].y;
+  // the far poles: e2 + 1, .., K - 1, 0, .., e1 - 1 (the same count on every
+  // lane of the block, so the lanes' loops stay in step)
+  const double2* far = dw + e2 + 1;
+  const int nfar = K - 2;
   conv = false;
   for (int it = 0; it < kSecularMaxIts; ++it) {
-    // two partial sums per accumulator halve the dependent chain
-    double pl0 = 0.0, dpl0 = 0.0, pl1 = 0.0, dpl1 = 0.0;
-    double ph0 = 0.0, dph0 = 0.0, ph1 = 0.0, dph1 = 0.0;
-    int j = 0;
+    // F, sum |terms|, F' and F''/2 of the far terms at tau, in two chains
+    double F0 = 0.0, A0 = 0.0, D0 = 0.0, E0 = 0.0;
+    double F1 = 0.0, A1 = 0.0, D1 = 0.0, E1 = 0.0;
+    int o = 0;
 #pragma unroll 4
-    for (; j + 1 < e1; j += 2) {
-      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
-      const double t1 = w[j + 1] * frcp((d[j + 1] - dorg) - tau);
-      pl0 = fma(t0, w[j], pl0);
-      dpl0 = fma(t0, t0, dpl0);
-      pl1 = fma(t1, w[j + 1], pl1);
-      dpl1 = fma(t1, t1, dpl1);
+    for (; o + 1 < nfar; o += 2) {
+      const double2 p = far[o], q = far[o + 1];
+      const double r0 = frcp((p.x - dorg) - tau);
+      const double r1 = frcp((q.x - dorg) - tau);
+      const double t0 = p.y * p.y * r0, t1 = q.y * q.y * r1;
+      const double u0 = t0 * r0, u1 = t1 * r1;
+      F0 += t0;
+      A0 += fabs(t0);
+      D0 += u0;
+      E0 = fma(u0, r0, E0);
+      F1 += t1;
+      A1 += fabs(t1);
+      D1 += u1;
+      E1 = fma(u1, r1, E1);
     }
-    if (j < e1) {
-      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
-      pl0 = fma(t0, w[j], pl0);
-      dpl0 = fma(t0, t0, dpl0);
+    if (o < nfar) {
+      const double2 p = far[o];
+      const double r0 = frcp((p.x - dorg) - tau);
+      const double t0 = p.y * p.y * r0;
+      const double u0 = t0 * r0;
+      F0 += t0;
+      A0 += fabs(t0);
+      D0 += u0;
+      E0 = fma(u0, r0, E0);
     }
-    j = e2 + 1;
-#pragma unroll 4
-    for (; j + 1 < K; j += 2) {
-      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
-      const double t1 = w[j + 1] * frcp((d[j + 1] - dorg) - tau);
-      ph0 = fma(t0, w[j], ph0);
-      dph0 = fma(t0, t0, dph0);
-      ph1 = fma(t1, w[j + 1], ph1);
-      dph1 = fma(t1, t1, dph1);
-    }
-    if (j < K) {
-      const double t0 = w[j] * frcp((d[j] - dorg) - tau);
-      ph0 = fma(t0, w[j], ph0);
-      dph0 = fma(t0, t0, dph0);
-    }
-    const double pl = pl0 + pl1, dpl = dpl0 + dpl1, ph = ph0 + ph1, dph = dph0 + dph1;
+    const double F = F0 + F1, A = A0 + A1, Fd = D0 + D1, Fh = E0 + E1;
     const double g1 = P1 - tau, g2 = P2 - tau;
     const double t1 = e1 >= 0 ? W1 * frcp(g1) : 0.0;
     const double t2 = W2 * frcp(g2);
-    const double f = irho + pl + ph + t1 + t2;
-    if (fabs(f) <= 4.0 * kDcEps * K * (irho + fabs(pl) + fabs(ph) + fabs(t1) + fabs(t2))) {
+    const double f = irho + F + t1 + t2;
+    if (fabs(f) <= 4.0 * kDcEps * K * (irho + A + fabs(t1) + fabs(t2))) {
       conv = true;
       break;
     }
@@ -206,8 +216,18 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
       conv = true;
       break;
     }
-    const double c0 = irho + (pl - dpl * g1) + (ph - dph * g2);
-    const double B1 = W1 + dpl * g1 * g1, B2 = W2 + dph * g2 * g2;
+    // split of F' over the model poles: a1 = s1/g1^2, a2 = s2/g2^2
+    double a1, a2;
+    if (last) {
+      a1 = Fd;
+      a2 = 0.0;
+    } else {
+      const double ig = frcp(g2 - g1);
+      a1 = fmax((Fh * g2 - Fd) * g1 * ig, 0.0);
+      a2 = fmax((Fd - Fh * g1) * g2 * ig, 0.0);
+    }
+    const double c0 = irho + F - a1 * g1 - a2 * g2;
+    const double B1 = W1 + a1 * g1 * g1, B2 = W2 + a2 * g2 * g2;
     double tn;
     if (!last) {
       tn = two_pole_root(c0, B1, B2, P1, P2, lo, hi);
@@ -227,8 +247,9 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
     }
     const bool inside = tn > lo && tn < hi;
     const double tnew = inside ? tn : 0.5 * (lo + hi);
-    // a model step (not a bisection) this small has converged: the model is
-    // exact to second order, so the next step would move tau by an ulp
+    // a model step (not a bisection) this small has converged: the model
+    // matches f to second order or better, so the next step would move tau
+    // by an ulp
     const bool done = inside && fabs(tnew - tau) <= 2.0 * kDcEps * fabs(tnew);
     tau = tnew;
     if (done) {
@@ -244,11 +265,13 @@ __device__ __forceinline__ int secular_root(const double* d, const double* w, in
 // of T) is position t = jj % S of block a = jj - t.  qs[0..S/2) holds, on
 // entry, row jj of the child's eigenvector matrix restricted to the child's
 // columns; on exit it holds row jj of the merged block's eigenvector matrix
-// restricted to the block's columns (qs[0..S)).  W is this matrix's LDS
-// scratch for the merge matrices (KP * (KP + 1) doubles).
+// restricted to the block's columns (qs[0..S)); lam is the eigenvalue of
+// column jj of the child on entry, of the merged block on exit.  W is this
+// matrix's LDS scratch for the merge matrices (KP * (KP + 1) doubles).
 template <int KP, int S>
-__device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const double* e_orig,
-                                         double* W, int jj, double deps, bool& ok) {
+__device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP>& L,
+                                         const double* e_orig, double* W, int jj, double deps,
+                                         bool& ok) {
   constexpr int H = S / 2;
   constexpr int WS = S + 1;                  // row stride of a block's merge matrix
   const int t = jj & (S - 1);
@@ -267,7 +290,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   }
   const double beta = e_orig[m - 1];
   const bool flip = beta < 0.0;
-  const double D = flip ? -L.lam[jj] : L.lam[jj];
+  const double D = flip ? -lam : lam;
   L.dt[jj] = D;
   wave_lds_sync();
   const double z = L.zb[jj];
@@ -288,32 +311,45 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   const double tol = 8.0 * deps * fmax(group_max<S>(fabs(D)), rho);
   wave_lds_sync();
   // deflation: negligible weights (lane-parallel), then pairs of close poles
-  // (a sequential scan by one lane over the sorted order)
-  const bool small = !(fabs(rho * L.ws[a + t]) > tol);
+  // (a sequential scan by one lane over the sorted order).  A pair (p, k) of
+  // neighbouring surviving poles is rotated when |(d_k - d_p) c s| <= tol
+  // for the rotation (c, s) = (w_k, w_p) / |(w_p, w_k)| that zeroes w_p,
+  // i.e. |d_k - d_p| |w_k w_p| <= tol (w_p^2 + w_k^2).  The scan runs only in
+  // blocks where some pair passes that test with the unrotated values: a
+  // rotation changes only the pair it acts on, so without such a pair the
+  // scan would find none.
+  const uint64_t bmask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
+  const double wt = L.ws[a + t], dtt = L.ds[a + t];
+  const bool small = !(fabs(rho * wt) > tol);
   L.inv[a + t] = small ? -1 : 0;
   if (small) L.ws[a + t] = 0.0;
+  const bool live = !trivial && !small;
+  const uint64_t below = (__ballot(live) >> sh0) & bmask & ((1ull << t) - 1ull);
+  bool cand = false;
+  if (live && below != 0) {
+    const int pp = 63 - __clzll(below);
+    const double wp = L.ws[a + pp], dp = L.ds[a + pp];
+    cand = fabs(dtt - dp) * fabs(wt * wp) <= tol * fma(wp, wp, wt * wt);
+  }
+  const bool scan = ((__ballot(cand) >> sh0) & bmask) != 0;
+  if (t == 0) L.rot[a + S - 1] = 0;
   wave_lds_sync();
-  if (t == 0 && !trivial) {
+  if (t == 0 && scan) {
     int prev = -1, nrot = 0;
     double dp = 0.0, wp = 0.0;
 #pragma unroll 8
     for (int k = 0; k < S; ++k) {
       const double wk = L.ws[a + k], dk = L.ds[a + k];
       if (L.inv[a + k] >= 0) {
-        bool rot = false;
-        double c = 0.0, sn = 0.0, tt = 0.0;
-        if (prev >= 0) {
-          tt = sqrt(fma(wp, wp, wk * wk));
-          c = wk / tt;
-          sn = wp / tt;
-          rot = fabs((dk - dp) * c * sn) <= tol;
-        }
+        const bool rot =
+            prev >= 0 && fabs(dk - dp) * fabs(wk * wp) <= tol * fma(wp, wp, wk * wk);
         if (rot) {
+          const double tt = sqrt(fma(wp, wp, wk * wk));
+          const double c = wk / tt, sn = wp / tt;
           L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
           L.ws[a + prev] = 0.0;
           L.inv[a + prev] = -1;
-          L.rp[a + nrot] = prev;
-          L.rj[a + nrot] = k;
+          L.rot[a + nrot] = prev | (k << 8);
           L.rc[a + nrot] = c;
           L.rs[a + nrot] = sn;
           ++nrot;
@@ -328,7 +364,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
         prev = k;
       }
     }
-    L.nr[a] = nrot;
+    L.rot[a + S - 1] = nrot;
   }
   wave_lds_sync();
   // keep list: non-deflated sorted positions in order
@@ -338,39 +374,35 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
   const int kidx = __popcll(kmask & ((1ull << t) - 1ull));
   if (keep) {
     L.inv[a + t] = kidx;
-    L.kp[a + kidx] = t;
     L.rw[a + kidx] = L.pm[a + t];
-    L.dk[a + kidx] = L.ds[a + t];
-    L.wk[a + kidx] = L.ws[a + t];
-  }
-  if (t >= K) {                                    // padding of the secular arrays
-    L.dk[a + t] = kFarPole;
-    L.wk[a + t] = 0.0;
+    const double2 pr = make_double2(L.ds[a + t], L.ws[a + t]);
+    L.dw[2 * a + kidx] = pr;
+    L.dw[2 * a + K + kidx] = pr;
   }
   wave_lds_sync();
   // secular roots, one per lane
   if (t < K) {
     double tau;
     bool conv;
-    const int org = secular_root<S>(L.dk + a, L.wk + a, K, t, rho, tau, conv);
+    const int org = secular_root(L.dw + 2 * a, K, t, rho, tau, conv);
     if (!conv) ok = false;
-    L.rd[a + t] = L.dk[a + org];
+    L.rd[a + t] = L.dw[2 * a + org].x;
     L.rt[a + t] = tau;
   }
   wave_lds_sync();
   // Loewner: zhat_j^2 = (1/rho) prod_i (lambda_i - d_j) / prod_{i != j} (d_i - d_j)
   if (t < K) {
-    const double dj = L.dk[a + t];
+    const double dj = L.dw[2 * a + t].x;
     double prod = 1.0 / rho;
 #pragma unroll 8
     for (int i = 0; i < S; ++i) {
       if (i < K) {
         const double num = (L.rd[a + i] - dj) + L.rt[a + i];
-        prod *= i == t ? num : num * frcp(L.dk[a + i] - dj);
+        prod *= i == t ? num : num * frcp(L.dw[2 * a + i].x - dj);
       }
     }
     const double zr = sqrt(fmax(prod, 0.0));
-    L.zh[a + t] = L.wk[a + t] >= 0.0 ? zr : -zr;
+    L.zh[a + t] = L.dw[2 * a + t].y >= 0.0 ? zr : -zr;
   }
   if (t >= K) L.zh[a + t] = 0.0;
   wave_lds_sync();
@@ -392,7 +424,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
       double nrm = 0.0;
 #pragma unroll 8
       for (int u = 0; u < K; ++u) {
-        const double v = L.zh[a + u] * frcp((L.dk[a + u] - dorg) - tau);
+        const double v = L.zh[a + u] * frcp((L.dw[2 * a + u].x - dorg) - tau);
         nrm = fma(v, v, nrm);
         Wb[L.rw[a + u] * WS + t] = v;
       }
@@ -402,17 +434,18 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
       lam_new = dorg + tau;
     }
     // deflation rotations, last first, on rows pm[p], pm[j] of this column
-    const int nrot = L.nr[a];
+    const int nrot = L.rot[a + S - 1];
     for (int q = nrot - 1; q >= 0; --q) {
-      const int rpi = L.pm[a + L.rp[a + q]] * WS + t;
-      const int rji = L.pm[a + L.rj[a + q]] * WS + t;
+      const int pj = L.rot[a + q];
+      const int rpi = L.pm[a + (pj & 255)] * WS + t;
+      const int rji = L.pm[a + (pj >> 8)] * WS + t;
       const double c = L.rc[a + q], sn = L.rs[a + q];
       const double xp = Wb[rpi], xj = Wb[rji];
       Wb[rpi] = fma(c, xp, sn * xj);
       Wb[rji] = fma(-sn, xp, c * xj);
     }
   }
-  L.lam[jj] = flip ? -lam_new : lam_new;
+  lam = flip ? -lam_new : lam_new;
   wave_lds_sync();
   // this lane's row of the merged block's eigenvector matrix
   const int h0 = t < H ? 0 : H;              // first W row of this lane's child
@@ -432,30 +465,30 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], DcLds<KP>& L, const d
 }
 
 template <int KP, int S>
-__device__ __forceinline__ void dc_levels(double (&qs)[KP], DcLds<KP>& L, const double* e_orig,
-                                          double* W, int jj, double deps, bool& ok) {
+__device__ __forceinline__ void dc_levels(double (&qs)[KP], double& lam, DcLds<KP>& L,
+                                          const double* e_orig, double* W, int jj, double deps,
+                                          bool& ok) {
   if constexpr (S <= KP) {
-    dc_merge<KP, S>(qs, L, e_orig, W, jj, deps, ok);
-    dc_levels<KP, 2 * S>(qs, L, e_orig, W, jj, deps, ok);
+    dc_merge<KP, S>(qs, lam, L, e_orig, W, jj, deps, ok);
+    dc_levels<KP, 2 * S>(qs, lam, L, e_orig, W, jj, deps, ok);
   }
 }
 
 // Eigen-decomposition of the tridiagonal (d, e) (LDS, KP entries each; e
 // is not modified).  Deflation tolerance 8 deps max(|D|, rho) per merge, with
 // deps the unit roundoff of the arithmetic that produced the matrix.  On
-// return L.lam[jj] is the eigenvalue of column jj and
-// qs[] is row jj of the eigenvector matrix.  Returns false if a secular root
-// ran out of iterations.
+// return lam is the eigenvalue of column jj and qs[] is row jj of the
+// eigenvector matrix.  Returns false if a secular root ran out of iterations.
 template <int KP>
-__device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], DcLds<KP>& L, const double* d,
-                                               const double* e, double* W, int jj, double deps) {
+__device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], double& lam, DcLds<KP>& L,
+                                               const double* d, const double* e, double* W, int jj,
+                                               double deps) {
   const double el = jj > 0 ? e[jj - 1] : 0.0;
-  L.lam[jj] = d[jj] - el - e[jj];            // leaves after tearing every coupling
+  lam = d[jj] - el - e[jj];                  // leaves after tearing every coupling
 #pragma unroll
   for (int c = 0; c < KP; ++c) qs[c] = c == 0 ? 1.0 : 0.0;
-  wave_lds_sync();
   bool ok = true;
-  dc_levels<KP, 2>(qs, L, e, W, jj, deps, ok);
+  dc_levels<KP, 2>(qs, lam, L, e, W, jj, deps, ok);
   return ok;
 }
 

@@ -454,13 +454,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   tridiagonalize<KP>(a, sh, seg, jj);
   if constexpr (KP > 32) store_reflectors<KP>(a, rv, e.k, jj, valid);
   double q[KP];
+  double lam;
   const bool conv =
-      dc_tridiagonal<KP>(q, sh.dc[seg], sh.d[seg], sh.e[seg], sh.mat[seg], jj, e.defl_eps);
+      dc_tridiagonal<KP>(q, lam, sh.dc[seg], sh.d[seg], sh.e[seg], sh.mat[seg], jj, e.defl_eps);
   // any lane of the matrix whose secular root ran out of iterations
   const uint64_t segmask = KP == 64 ? ~0ull : (((1ull << KP) - 1ull) << (seg * KP));
   const bool all_conv = (__ballot(!conv) & segmask) == 0;
   if (!all_conv && jj == 0 && valid && e.status) atomicOr(e.status, kStatNotconv);
-  const double lam = sh.dc[seg].lam[jj];
   wave_lds_sync();
   back_transform<KP>(q, a, rv, e.k, sh, seg, jj);
   if (e.mode != 0) {
