@@ -156,30 +156,61 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
   vb[jj] = vj;
   wave_lds_sync();
-  // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
-  double p0 = 0.0, p1 = 0.0;
+  if constexpr (KP <= 32) {
+    // the trailing parts of v and w go to registers in one burst of LDS
+    // reads each (one wait per vector instead of one per few products)
+    constexpr int c0 = (i + 1) & ~1;
+    double vv[KP], ww[KP];
 #pragma unroll
-  for (int c = i + 1; c < KP; ++c) {
-    if ((c & 1) == 0)
-      p0 = fma(a[c], vb[c], p0);
-    else
-      p1 = fma(a[c], vb[c], p1);
-    if ((c & 7) == 7) asm volatile("" ::: "memory");
-  }
-  const double p = jj > i ? (p0 + p1) * tau : 0.0;
-  const double K = 0.5 * tau * group_sum<KP>(p * vj);
-  const double w = fma(-K, vj, p);
-  wb[jj] = w;
-  wave_lds_sync();
-  // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
-  // v is read again through a fresh offset rather than kept live from above
-  const int so2 = opaque(so);
-  const double* vb2 = &sh.vb[0][0] + so2;
-  const double* wb2 = &sh.wb[0][0] + so2;
+    for (int c = c0; c < KP; c += 2) {
+      const double2 t2 = *reinterpret_cast<const double2*>(vb + c);
+      vv[c] = t2.x;
+      vv[c + 1] = t2.y;
+    }
+    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+    double pc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c = i + 1; c < KP; ++c) {
-    a[c] -= fma(vj, wb2[c], w * vb2[c]);
-    if ((c & 7) == 7) asm volatile("" ::: "memory");
+    for (int c = i + 1; c < KP; ++c) pc[c & 3] = fma(a[c], vv[c], pc[c & 3]);
+    const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
+    const double K = 0.5 * tau * group_sum<KP>(p * vj);
+    const double w = fma(-K, vj, p);
+    wb[jj] = w;
+    wave_lds_sync();
+#pragma unroll
+    for (int c = c0; c < KP; c += 2) {
+      const double2 t2 = *reinterpret_cast<const double2*>(wb + c);
+      ww[c] = t2.x;
+      ww[c + 1] = t2.y;
+    }
+    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0)
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) a[c] = fma(-w, vv[c], fma(-vj, ww[c], a[c]));
+  } else {
+    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      if ((c & 1) == 0)
+        p0 = fma(a[c], vb[c], p0);
+      else
+        p1 = fma(a[c], vb[c], p1);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
+    const double p = jj > i ? (p0 + p1) * tau : 0.0;
+    const double K = 0.5 * tau * group_sum<KP>(p * vj);
+    const double w = fma(-K, vj, p);
+    wb[jj] = w;
+    wave_lds_sync();
+    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
+    // v is read again through a fresh offset rather than kept live from above
+    const int so2 = opaque(so);
+    const double* vb2 = &sh.vb[0][0] + so2;
+    const double* wb2 = &sh.wb[0][0] + so2;
+#pragma unroll
+    for (int c = i + 1; c < KP; ++c) {
+      a[c] -= fma(vj, wb2[c], w * vb2[c]);
+      if ((c & 7) == 7) asm volatile("" ::: "memory");
+    }
   }
   // nothing of the next step may be scheduled into this one (the
   // interleaving would keep two copies of the row live)
@@ -257,6 +288,41 @@ __device__ __forceinline__ void apply_reflectors(double (&q)[KP], EvdLds<KP>& sh
   (apply_reflector<KP, KP - 3 - Is>(q, sh, seg), ...);
 }
 
+// Entries i+1 .. KP-1 of reflector i (row i of the matrix area, stride KP)
+// into registers, two per LDS read (from the even entry at or below i+1).
+template <int KP, int i>
+__device__ __forceinline__ void load_reflector(double (&v)[KP], const double* rows) {
+  constexpr int c0 = (i + 1) & ~1;
+#pragma unroll
+  for (int r = c0; r < KP; r += 2) {
+    const double2 t2 = *reinterpret_cast<const double2*>(rows + i * KP + r);
+    v[r] = t2.x;
+    v[r + 1] = t2.y;
+  }
+}
+
+// H_i .. H_0 applied to this lane's column q (KP <= 32), reflector i taken
+// from registers (cur) while reflector i-1 is read into the other set: the
+// LDS latency of a reflector hides behind the products of the one before.
+template <int KP, int i>
+__device__ __forceinline__ void apply_reflectors_pipelined(double (&q)[KP], double (&cur)[KP],
+                                                           const double* rows,
+                                                           const double* taus) {
+  double nxt[KP];
+  if constexpr (i > 0) load_reflector<KP, i - 1>(nxt, rows);
+  const double t = taus[i];
+  double dc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = i + 1; r < KP; ++r) dc[r & 3] = fma(q[r], cur[r], dc[r & 3]);
+  const double f = t * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
+#pragma unroll
+  for (int r = i + 1; r < KP; ++r) q[r] = fma(-f, cur[r], q[r]);
+  // no instruction of the next reflector ahead of this point (it would keep
+  // a third reflector's registers live)
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (i > 0) apply_reflectors_pipelined<KP, i - 1>(q, nxt, rows, taus);
+}
+
 // V = H Q_T with H = H_0 H_1 .. H_{n-3}: q holds row jj of Q_T on entry.
 // Q_T goes through the matrix area to give this lane column jj; the
 // reflectors follow it there as rows (stride KP), from this lane's registers
@@ -287,7 +353,14 @@ __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a
     for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = v[i];
   }
   wave_lds_sync();
-  apply_reflectors<KP>(q, sh, seg, std::make_integer_sequence<int, KP - 2>{});
+  if constexpr (KP <= 32) {
+    const double* rows = &sh.mat[0][0] + opaque(seg * KP * (KP + 1));
+    double cur[KP];
+    load_reflector<KP, KP - 3>(cur, rows);
+    apply_reflectors_pipelined<KP, KP - 3>(q, cur, rows, sh.tau[seg]);
+  } else {
+    apply_reflectors<KP>(q, sh, seg, std::make_integer_sequence<int, KP - 2>{});
+  }
   wave_lds_sync();
 #pragma unroll
   for (int r = 0; r < KP; ++r) M[r * S + jj] = q[r];
