@@ -133,6 +133,71 @@ __device__ __forceinline__ void load_rows(const double* M, int jj, double (&a)[K
   for (int u = 0; u < KP; ++u) a[u] = M[jj * S + u];
 }
 
+constexpr int cmin(int x, int y) { return x < y ? x : y; }
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// Entries [C0, C1) of an LDS vector (C0 even, 16-byte aligned base) into v[],
+// two per read.
+template <int KP, int C0, int C1>
+__device__ __forceinline__ void load_pairs(double (&v)[KP], const double* src) {
+#pragma unroll
+  for (int c = C0; c < C1; c += 2) {
+    const double2 t2 = *reinterpret_cast<const double2*>(src + c);
+    v[c] = t2.x;
+    v[c + 1] = t2.y;
+  }
+}
+
+// Streaming forms for rows too long to hold beside a second vector in
+// registers (KP = 64): the vector comes from LDS in chunks of CH entries,
+// chunk CS + CH being read while chunk CS (already requested) is used, and no
+// instruction crosses a chunk boundary, so at most two chunks are live.
+//   pc[c % 4] += x[c] v[c] for c in [LO, KP)
+template <int KP, int LO, int CS, int CH>
+__device__ __forceinline__ void dot_stream(const double (&x)[KP], const double* vsrc,
+                                           double (&v)[KP], double (&pc)[4]) {
+  if constexpr (CS < KP) {
+    constexpr int NS = CS + CH;
+    if constexpr (NS < KP) load_pairs<KP, NS, cmin(NS + CH, KP)>(v, vsrc);
+#pragma unroll
+    for (int c = cmax(CS, LO); c < cmin(NS, KP); ++c) pc[c & 3] = fma(x[c], v[c], pc[c & 3]);
+    __builtin_amdgcn_sched_barrier(0);
+    dot_stream<KP, LO, NS, CH>(x, vsrc, v, pc);
+  }
+}
+
+//   x[c] -= f v[c] for c in [LO, KP)
+template <int KP, int LO, int CS, int CH>
+__device__ __forceinline__ void axpy_stream(double (&x)[KP], const double* vsrc, double (&v)[KP],
+                                            double f) {
+  if constexpr (CS < KP) {
+    constexpr int NS = CS + CH;
+    if constexpr (NS < KP) load_pairs<KP, NS, cmin(NS + CH, KP)>(v, vsrc);
+#pragma unroll
+    for (int c = cmax(CS, LO); c < cmin(NS, KP); ++c) x[c] = fma(-f, v[c], x[c]);
+    __builtin_amdgcn_sched_barrier(0);
+    axpy_stream<KP, LO, NS, CH>(x, vsrc, v, f);
+  }
+}
+
+//   x[c] -= vj w[c] + wj v[c] for c in [LO, KP)
+template <int KP, int LO, int CS, int CH>
+__device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc,
+                                             const double* wsrc, double (&v)[KP],
+                                             double (&w)[KP], double vj, double wj) {
+  if constexpr (CS < KP) {
+    constexpr int NS = CS + CH;
+    if constexpr (NS < KP) {
+      load_pairs<KP, NS, cmin(NS + CH, KP)>(v, vsrc);
+      load_pairs<KP, NS, cmin(NS + CH, KP)>(w, wsrc);
+    }
+#pragma unroll
+    for (int c = cmax(CS, LO); c < cmin(NS, KP); ++c) x[c] = fma(-wj, v[c], fma(-vj, w[c], x[c]));
+    __builtin_amdgcn_sched_barrier(0);
+    rank2_stream<KP, LO, NS, CH>(x, vsrc, wsrc, v, w, vj, wj);
+  }
+}
+
 // Householder tridiagonalization of the symmetric matrix whose row jj this
 // lane holds in a[].  Step i annihilates A[i+2:, i] with H_i = I - tau v v^T,
 // v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
@@ -186,31 +251,23 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
 #pragma unroll
     for (int c = i + 1; c < KP; ++c) a[c] = fma(-w, vv[c], fma(-vj, ww[c], a[c]));
   } else {
+    constexpr int c0 = (i + 1) & ~1;
+    double vv[KP], ww[KP];
     // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
-    double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      if ((c & 1) == 0)
-        p0 = fma(a[c], vb[c], p0);
-      else
-        p1 = fma(a[c], vb[c], p1);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
-    }
-    const double p = jj > i ? (p0 + p1) * tau : 0.0;
+    constexpr int CH = 16;
+    load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, vb);
+    double pc[4] = {0.0, 0.0, 0.0, 0.0};
+    dot_stream<KP, i + 1, c0, CH>(a, vb, vv, pc);
+    const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
     const double K = 0.5 * tau * group_sum<KP>(p * vj);
     const double w = fma(-K, vj, p);
     wb[jj] = w;
     wave_lds_sync();
-    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0);
-    // v is read again through a fresh offset rather than kept live from above
-    const int so2 = opaque(so);
-    const double* vb2 = &sh.vb[0][0] + so2;
-    const double* wb2 = &sh.wb[0][0] + so2;
-#pragma unroll
-    for (int c = i + 1; c < KP; ++c) {
-      a[c] -= fma(vj, wb2[c], w * vb2[c]);
-      if ((c & 7) == 7) asm volatile("" ::: "memory");
-    }
+    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0)
+    constexpr int CH2 = 8;
+    load_pairs<KP, c0, cmin(c0 + CH2, KP)>(vv, vb);
+    load_pairs<KP, c0, cmin(c0 + CH2, KP)>(ww, wb);
+    rank2_stream<KP, i + 1, c0, CH2>(a, vb, wb, vv, ww, vj, w);
   }
   // nothing of the next step may be scheduled into this one (the
   // interleaving would keep two copies of the row live)
@@ -258,36 +315,6 @@ __device__ __forceinline__ void store_reflectors(const double (&a)[KP], double* 
     if (i < jj) rv[refl_pos(i, jj, k)] = a[i];
 }
 
-// Applies reflector I (row I of the matrix area, stride KP) to this lane's
-// column q of Q_T (see back_transform).
-template <int KP, int i>
-__device__ __forceinline__ void apply_reflector(double (&q)[KP], EvdLds<KP>& sh, int seg) {
-  const double t = sh.tau[seg][i];
-  const double* v = &sh.mat[0][0] + opaque(seg * KP * (KP + 1)) + i * KP;
-  double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-  for (int r = i + 1; r < KP; ++r) {
-    if ((r & 1) == 0)
-      d0 = fma(q[r], v[r], d0);
-    else
-      d1 = fma(q[r], v[r], d1);
-    if ((r & 7) == 7) asm volatile("" ::: "memory");
-  }
-  const double f = t * (d0 + d1);
-#pragma unroll
-  for (int r = i + 1; r < KP; ++r) {
-    q[r] = fma(-f, v[r], q[r]);
-    if ((r & 7) == 7) asm volatile("" ::: "memory");
-  }
-}
-
-template <int KP, int... Is>
-__device__ __forceinline__ void apply_reflectors(double (&q)[KP], EvdLds<KP>& sh, int seg,
-                                                 std::integer_sequence<int, Is...>) {
-  // H_{n-3} first, H_0 last
-  (apply_reflector<KP, KP - 3 - Is>(q, sh, seg), ...);
-}
-
 // Entries i+1 .. KP-1 of reflector i (row i of the matrix area, stride KP)
 // into registers, two per LDS read (from the even entry at or below i+1).
 template <int KP, int i>
@@ -299,6 +326,29 @@ __device__ __forceinline__ void load_reflector(double (&v)[KP], const double* ro
     v[r] = t2.x;
     v[r + 1] = t2.y;
   }
+}
+
+// H_i applied to this lane's column q, the reflector streamed from LDS (KP = 64).
+template <int KP, int i>
+__device__ __forceinline__ void apply_reflector_stream(double (&q)[KP], const double* rows,
+                                                       const double* taus) {
+  constexpr int c0 = (i + 1) & ~1;
+  constexpr int CH = 16;
+  const double* v = rows + i * KP;
+  double vv[KP];
+  load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, v);
+  double pc[4] = {0.0, 0.0, 0.0, 0.0};
+  dot_stream<KP, i + 1, c0, CH>(q, v, vv, pc);
+  const double f = taus[i] * ((pc[0] + pc[1]) + (pc[2] + pc[3]));
+  load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, v);
+  axpy_stream<KP, i + 1, c0, CH>(q, v, vv, f);
+}
+
+template <int KP, int... Is>
+__device__ __forceinline__ void apply_reflectors_stream(double (&q)[KP], const double* rows,
+                                                        const double* taus,
+                                                        std::integer_sequence<int, Is...>) {
+  (apply_reflector_stream<KP, KP - 3 - Is>(q, rows, taus), ...);
 }
 
 // H_i .. H_0 applied to this lane's column q (KP <= 32), reflector i taken
@@ -359,7 +409,8 @@ __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a
     load_reflector<KP, KP - 3>(cur, rows);
     apply_reflectors_pipelined<KP, KP - 3>(q, cur, rows, sh.tau[seg]);
   } else {
-    apply_reflectors<KP>(q, sh, seg, std::make_integer_sequence<int, KP - 2>{});
+    const double* rows = &sh.mat[0][0] + opaque(seg * KP * (KP + 1));
+    apply_reflectors_stream<KP>(q, rows, sh.tau[seg], std::make_integer_sequence<int, KP - 2>{});
   }
   wave_lds_sync();
 #pragma unroll
