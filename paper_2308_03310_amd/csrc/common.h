@@ -30,6 +30,15 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// p[i] read as global memory.  Pointers that arrive inside a descriptor are
+// generic to the compiler, and a generic (flat) load counts against the LDS
+// wait counter too, so a wait for an LDS read would also wait for it; a
+// global load keeps the two streams apart.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, size_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
 // Make LDS writes of this wavefront visible to its other lanes (and keep the
 // compiler from moving LDS accesses across this point).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -12,55 +12,10 @@
 // ring entries feed one K=4 step of v_mfma_f64_16x16x4f64 per upper 16x16
 // block of C.  The local observation set is never materialized in HBM.
 #include "common.h"
+#include "k_window.h"
 #include "launch.h"
 
 namespace letkf {
-
-__device__ __forceinline__ double gaspari_cohn(double r, double invc) {
-  // Gaspari & Cohn (1999) eq. (4.10), half-width c: zero for r >= 2c.
-  const double z = r * invc;
-  if (z <= 1.0) {
-    return (((-0.25 * z + 0.5) * z + 0.625) * z - 5.0 / 3.0) * z * z + 1.0;
-  }
-  if (z < 2.0) {
-    return ((((z / 12.0 - 0.5) * z + 0.625) * z + 5.0 / 3.0) * z - 5.0) * z + 4.0 - 2.0 / (3.0 * z);
-  }
-  return 0.0;
-}
-
-// Cell intervals (at most two, merged when they touch) covering lattice
-// coordinates [c - R, c + R] modulo n.
-__device__ __forceinline__ int cell_intervals(int c, int R, int n, int cb, int nc, int* lo, int* hi) {
-  if (R < 0 || 2 * R + 1 >= n) {
-    lo[0] = 0;
-    hi[0] = nc - 1;
-    return 1;
-  }
-  int a = c - R, b = c + R;
-  if (a >= 0 && b < n) {
-    lo[0] = a / cb;
-    hi[0] = b / cb;
-    return 1;
-  }
-  int lo1, hi2;
-  if (a < 0) {
-    lo1 = (a + n) / cb;
-    hi2 = b / cb;
-  } else {
-    lo1 = a / cb;
-    hi2 = (b - n) / cb;
-  }
-  if (hi2 + 1 >= lo1) {
-    lo[0] = 0;
-    hi[0] = nc - 1;
-    return 1;
-  }
-  lo[0] = 0;
-  hi[0] = hi2;
-  lo[1] = lo1;
-  hi[1] = nc - 1;
-  return 2;
-}
 
 template <int KQ>
 struct GramAcc {
@@ -70,52 +25,113 @@ struct GramAcc {
   double bacc[NQ];
 };
 
+// Ring entry head + lane / 16 of one K = 4 step.  Every slot of the ring
+// always holds a valid observation index and a finite weight (the ring is
+// cleared when a point starts), so the reads need no branch; entries past the
+// tail get weight 0 and contribute exact zeros.
+struct RingRef {
+  int s;
+  double w, live;   // live: 1 for an entry before the tail, else 0
+};
+
+__device__ __forceinline__ RingRef ring_ref(const int* ring_s, const double* ring_w, int head,
+                                            int tail) {
+  const int idx = head + (lane_id() >> 4);
+  const int slot = idx & (kRing - 1);
+  RingRef r;
+  r.s = ring_s[slot];
+  r.w = ring_w[slot];
+  r.live = idx < tail ? 1.0 : 0.0;
+  return r;
+}
+
+// Operands of one step: the weight, the innovation and the lane's entries of
+// the dy row of its ring entry.
 template <int KQ>
-__device__ __forceinline__ void gram_step(GramAcc<KQ>& acc, const GramArgs& g, const int* ring_s,
-                                          const double* ring_w, int head, int tail) {
+struct GramStepF64 {
+  double w, dv;
+  double yv[KQ / 16];
+};
+
+template <int KQ>
+__device__ __forceinline__ GramStepF64<KQ> gram_load(const GramArgs& g, const RingRef& r) {
   constexpr int NQ = KQ / 16;
-  const int lane = lane_id();
-  const int e = lane >> 4, col = lane & 15;
-  const int idx = head + e;
-  // Entries past the tail (last, partial step) contribute exact zeros.
-  double w = 0.0, dv = 0.0;
-  double yv[NQ], av[NQ];
+  GramStepF64<KQ> st;
+  st.w = r.w * r.live;
+  st.dv = ldg(g.d, r.s);
+  const double* row = g.Yb + (size_t)r.s * KQ + (lane_id() & 15);
 #pragma unroll
-  for (int I = 0; I < NQ; ++I) yv[I] = 0.0;
-  if (idx < tail) {
-    const int s = ring_s[idx & 127];
-    w = ring_w[idx & 127];
-    dv = g.d[s];
-    const double* row = g.Yb + (size_t)s * KQ + col;
-#pragma unroll
-    for (int I = 0; I < NQ; ++I) yv[I] = row[16 * I];
-  }
+  for (int I = 0; I < NQ; ++I) st.yv[I] = ldg(row, 16 * I);
+  return st;
+}
+
+template <int KQ>
+__device__ __forceinline__ void gram_accumulate(GramAcc<KQ>& acc, const GramStepF64<KQ>& st) {
+  constexpr int NQ = KQ / 16;
+  double av[NQ];
 #pragma unroll
   for (int I = 0; I < NQ; ++I) {
-    av[I] = w * yv[I];
-    acc.bacc[I] = fma(av[I], dv, acc.bacc[I]);
+    av[I] = st.w * st.yv[I];
+    acc.bacc[I] = fma(av[I], st.dv, acc.bacc[I]);
   }
   int blk = 0;
 #pragma unroll
   for (int I = 0; I < NQ; ++I) {
 #pragma unroll
     for (int J = I; J < NQ; ++J) {
-      acc.c[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[I], yv[J], acc.c[blk], 0, 0, 0);
+      acc.c[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[I], st.yv[J], acc.c[blk], 0, 0, 0);
       ++blk;
     }
   }
 }
 
+// Every full step in the ring, software-pipelined over three stages: the
+// ring entries of step h + 8 are read from LDS and the dy rows of step h + 4
+// requested from memory while the MFMAs of step h run.  Two register sets
+// are used in turn (a copy from one to the other would wait for the loads in
+// flight); the sets read past the last full step are dropped.
+template <int KQ>
+__device__ __forceinline__ void gram_drain(GramAcc<KQ>& acc, const GramArgs& g, const int* ring_s,
+                                           const double* ring_w, int& head, int tail) {
+  const int n = (tail - head) >> 2;   // full steps
+  if (n == 0) return;
+  GramStepF64<KQ> sa = gram_load<KQ>(g, ring_ref(ring_s, ring_w, head, tail)), sb;
+  RingRef ra = ring_ref(ring_s, ring_w, head + 4, tail), rb;
+  // pairs of steps, one loop exit (exits between the two halves would give
+  // the accumulators two homes and copies between them); the scheduling
+  // barriers keep the compiler from moving the loads down to their use
+  for (int i = 0; i + 1 < n; i += 2) {
+    sb = gram_load<KQ>(g, ra);
+    rb = ring_ref(ring_s, ring_w, head + 8, tail);
+    __builtin_amdgcn_sched_barrier(0);
+    gram_accumulate<KQ>(acc, sa);
+    head += 4;
+    sa = gram_load<KQ>(g, rb);
+    ra = ring_ref(ring_s, ring_w, head + 8, tail);
+    __builtin_amdgcn_sched_barrier(0);
+    gram_accumulate<KQ>(acc, sb);
+    head += 4;
+  }
+  if (n & 1) {
+    gram_accumulate<KQ>(acc, sa);
+    head += 4;
+  }
+}
+
 // The localized Gram matrix and right-hand side of slab-local point pl, by
 // one wavefront; ring_s / ring_w are its LDS ring of local observations.
+// The loads of each candidate batch are issued before the ring filled by the
+// previous batch is drained.
 template <int KQ>
 __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* ring_s,
                                                double* ring_w) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   const int lane = lane_id();
-  const int gidx = bm.g0 + pl;
-  const int prob = find_problem(bm.prefix, bm.nprob, gidx);
+  // the point is the wavefront's: uniform, so its descriptor, window and
+  // cell table go through scalar registers and scalar loads
+  const int gidx = __builtin_amdgcn_readfirstlane(bm.g0 + pl);
+  const int prob = __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx));
   const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];  // point within its problem
@@ -127,57 +143,34 @@ __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* 
 #pragma unroll
   for (int I = 0; I < NQ; ++I) acc.bacc[I] = 0.0;
 
-  int xlo[2], xhi[2], ylo[2], yhi[2];
-  const int nxi = cell_intervals(x, g.R, g.nx, g.cb, g.ncx, xlo, xhi);
-  const int nyi = cell_intervals(y, g.R, g.ny, g.cb, g.ncy, ylo, yhi);
+  // clear the ring: every slot then holds a valid observation index (0; the
+  // walk below only runs when there are observations) and a finite weight
+  ring_s[lane] = 0;
+  ring_s[lane + 64] = 0;
+  ring_w[lane] = 0.0;
+  ring_w[lane + 64] = 0.0;
+  wave_lds_sync();
+
+  WindowCursor cur;
+  bool ok = window_begin(cur, g, x, y);
+  Candidate cand{0, 0, 0.0};
+  if (ok) cand = load_candidate(g, cur.s, cur.s1);
   int head = 0, tail = 0;
-  for (int yi = 0; yi < nyi; ++yi) {
-    for (int cy = ylo[yi]; cy <= yhi[yi]; ++cy) {
-      for (int xi = 0; xi < nxi; ++xi) {
-        const int s0 = g.cell_start[cy * g.ncx + xlo[xi]];
-        const int s1 = g.cell_start[cy * g.ncx + xhi[xi] + 1];
-        for (int base = s0; base < s1; base += 64) {
-          const int s = base + lane;
-          double w = 0.0;
-          if (s < s1) {
-            int dx = abs(x - g.ox[s]);
-            dx = min(dx, g.nx - dx);
-            int dy = abs(y - g.oy[s]);
-            dy = min(dy, g.ny - dy);
-            const int r2 = dx * dx + dy * dy;
-            const double rv = g.rinv[s];
-            const double r2d = (double)r2;
-            if (rv > 0.0 && r2d <= g.cut2) {
-              double gl;
-              if (g.loc == 0) {
-                gl = exp(-r2d * g.inv2L2);
-              } else if (g.loc == 1) {
-                gl = gaspari_cohn(sqrt(r2d), g.invL);
-              } else {
-                gl = 1.0;
-              }
-              w = gl * rv;
-            }
-          }
-          const bool in = w > 0.0;
-          const uint64_t mask = __ballot(in);
-          const int pos = __popcll(mask & ((1ull << lane) - 1ull));
-          if (in) {
-            ring_s[(tail + pos) & 127] = s;
-            ring_w[(tail + pos) & 127] = w;
-          }
-          tail += __popcll(mask);
-          wave_lds_sync();
-          while (tail - head >= 4) {
-            gram_step<KQ>(acc, g, ring_s, ring_w, head, tail);
-            head += 4;
-          }
-          wave_lds_sync();
-        }
-      }
-    }
+  while (ok) {
+    const int s = cur.s + lane;
+    const double w = candidate_weight(cand, g, x, y, s < cur.s1);
+    WindowCursor nx = cur;
+    const bool ok2 = window_next_batch(nx, g);
+    // the next batch's loads (this batch's again when there is none)
+    cand = ok2 ? load_candidate(g, nx.s, nx.s1) : load_candidate(g, cur.s, cur.s1);
+    tail = ring_append(ring_s, ring_w, tail, s, w);
+    wave_lds_sync();
+    gram_drain<KQ>(acc, g, ring_s, ring_w, head, tail);
+    wave_lds_sync();
+    cur = nx;
+    ok = ok2;
   }
-  if (tail > head) gram_step<KQ>(acc, g, ring_s, ring_w, head, tail);
+  if (tail > head) gram_accumulate<KQ>(acc, gram_load<KQ>(g, ring_ref(ring_s, ring_w, head, tail)));
 
   // b: sum the four K-groups (lanes col, col+16, col+32, col+48).
 #pragma unroll
@@ -206,8 +199,8 @@ __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* 
 // observation counts differ widely between points).
 template <int KQ, bool PERSIST>
 __global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
-  __shared__ int s_ring[4][128];
-  __shared__ double w_ring[4][128];
+  __shared__ int s_ring[4][kRing];
+  __shared__ double w_ring[4][kRing];
   const int wid = threadIdx.x >> 6;
   if constexpr (!PERSIST) {
     const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
