@@ -7,7 +7,10 @@
 //   FP32: v_mfma_f32_16x16x4f32      (4 local observations per K-step)
 //   BF16: v_mfma_f32_16x16x16bf16_1k (16 local observations per K-step)
 // C and b are written as FP64 for the FP64 eigensolve.
+#include <type_traits>
+
 #include "common.h"
+#include "k_window.h"
 #include "launch.h"
 
 namespace letkf {
@@ -18,48 +21,6 @@ typedef short short4_t __attribute__((ext_vector_type(4)));
 // f32_acc_row(l, r), column l % 16.
 __device__ __forceinline__ int f32_acc_row(int l, int r) { return 4 * (l >> 4) + r; }
 
-
-__device__ __forceinline__ double gc_weight(double r, double invc) {
-  const double z = r * invc;
-  if (z <= 1.0) return (((-0.25 * z + 0.5) * z + 0.625) * z - 5.0 / 3.0) * z * z + 1.0;
-  if (z < 2.0)
-    return ((((z / 12.0 - 0.5) * z + 0.625) * z + 5.0 / 3.0) * z - 5.0) * z + 4.0 - 2.0 / (3.0 * z);
-  return 0.0;
-}
-
-__device__ __forceinline__ int cell_intervals_lp(int c, int R, int n, int cb, int nc, int* lo,
-                                                 int* hi) {
-  if (R < 0 || 2 * R + 1 >= n) {
-    lo[0] = 0;
-    hi[0] = nc - 1;
-    return 1;
-  }
-  int a = c - R, b = c + R;
-  if (a >= 0 && b < n) {
-    lo[0] = a / cb;
-    hi[0] = b / cb;
-    return 1;
-  }
-  int lo1, hi2;
-  if (a < 0) {
-    lo1 = (a + n) / cb;
-    hi2 = b / cb;
-  } else {
-    lo1 = a / cb;
-    hi2 = (b - n) / cb;
-  }
-  if (hi2 + 1 >= lo1) {
-    lo[0] = 0;
-    hi[0] = nc - 1;
-    return 1;
-  }
-  lo[0] = 0;
-  hi[0] = hi2;
-  lo[1] = lo1;
-  hi[1] = nc - 1;
-  return 2;
-}
-
 template <int KQ, int PREC>
 struct GramAccLp {
   static constexpr int NQ = KQ / 16;
@@ -68,74 +29,95 @@ struct GramAccLp {
   float bacc[NQ];
 };
 
-// FP32: four ring entries per step, one per 16-lane group.
-template <int KQ>
-__device__ __forceinline__ void gram_step_f32(GramAccLp<KQ, 1>& acc, const GramArgs& g,
-                                              const int* ring_s, const double* ring_w, int head,
-                                              int tail) {
-  constexpr int NQ = KQ / 16;
-  const int lane = lane_id();
-  const int e = lane >> 4, col = lane & 15;
-  const int idx = head + e;
-  float w = 0.f, dv = 0.f;
-  float yv[NQ], av[NQ];
+// Ring entries of one step: R per lane (FP32: entry head + lane / 16; BF16:
+// entries head + 4 (lane / 16) + t, t < 4).  Every ring slot holds a valid
+// observation index and a finite weight (cleared when a point starts), so
+// the reads need no branch; entries past the tail get weight 0.
+template <int R>
+struct RingRefs {
+  int s[R];
+  float w[R], live[R];
+};
+
+template <int R>
+__device__ __forceinline__ RingRefs<R> ring_refs(const int* ring_s, const double* ring_w,
+                                                 int head, int tail) {
+  RingRefs<R> r;
+  const int base = head + R * (lane_id() >> 4);
 #pragma unroll
-  for (int I = 0; I < NQ; ++I) yv[I] = 0.f;
-  if (idx < tail) {
-    const int s = ring_s[idx & 127];
-    w = (float)ring_w[idx & 127];
-    dv = (float)g.d[s];
-    const float* row = reinterpret_cast<const float*>(g.Ylp) + (size_t)s * KQ + col;
-#pragma unroll
-    for (int I = 0; I < NQ; ++I) yv[I] = row[16 * I];
+  for (int t = 0; t < R; ++t) {
+    const int idx = base + t;
+    const int slot = idx & (kRing - 1);
+    r.s[t] = ring_s[slot];
+    r.w[t] = (float)ring_w[slot];
+    r.live[t] = idx < tail ? 1.f : 0.f;
   }
+  return r;
+}
+
+// Raw operands of one step as loaded: weights, innovations and the lane's
+// entries of the dy rows (FP32 values or BF16 bit patterns).
+template <int KQ, int R, typename E>
+struct GramStepLp {
+  float w[R], dv[R];
+  E y[R][KQ / 16];
+};
+
+template <int KQ, int R, typename E>
+__device__ __forceinline__ GramStepLp<KQ, R, E> gram_load_lp(const GramArgs& g,
+                                                             const RingRefs<R>& r) {
+  constexpr int NQ = KQ / 16;
+  const E* Y = reinterpret_cast<const E*>(g.Ylp);
+  const int col = lane_id() & 15;
+  GramStepLp<KQ, R, E> st;
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    st.w[t] = r.w[t] * r.live[t];
+    st.dv[t] = (float)ldg(g.d, r.s[t]);
+    const E* row = Y + (size_t)r.s[t] * KQ + col;
+#pragma unroll
+    for (int I = 0; I < NQ; ++I) st.y[t][I] = ldg(row, 16 * I);
+  }
+  return st;
+}
+
+// FP32: one entry per 16-lane group, K = 4.
+template <int KQ>
+__device__ __forceinline__ void gram_accumulate_lp(GramAccLp<KQ, 1>& acc,
+                                                   const GramStepLp<KQ, 1, float>& st) {
+  constexpr int NQ = KQ / 16;
+  float av[NQ];
 #pragma unroll
   for (int I = 0; I < NQ; ++I) {
-    av[I] = w * yv[I];
-    acc.bacc[I] = fmaf(av[I], dv, acc.bacc[I]);
+    av[I] = st.w[0] * st.y[0][I];
+    acc.bacc[I] = fmaf(av[I], st.dv[0], acc.bacc[I]);
   }
   int blk = 0;
 #pragma unroll
   for (int I = 0; I < NQ; ++I) {
 #pragma unroll
     for (int J = I; J < NQ; ++J) {
-      acc.c[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[I], yv[J], acc.c[blk], 0, 0, 0);
+      acc.c[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[I], st.y[0][J], acc.c[blk], 0, 0, 0);
       ++blk;
     }
   }
 }
 
-// BF16: sixteen ring entries per step, four per 16-lane group.
+// BF16: four entries per 16-lane group, K = 16; the weighted operand is
+// rounded to BF16 and the right-hand side accumulates that rounded value.
 template <int KQ>
-__device__ __forceinline__ void gram_step_bf16(GramAccLp<KQ, 2>& acc, const GramArgs& g,
-                                               const int* ring_s, const double* ring_w, int head,
-                                               int tail) {
+__device__ __forceinline__ void gram_accumulate_lp(GramAccLp<KQ, 2>& acc,
+                                                   const GramStepLp<KQ, 4, unsigned short>& st) {
   constexpr int NQ = KQ / 16;
-  const int lane = lane_id();
-  const int q = lane >> 4, col = lane & 15;
   short4_t A[NQ], B[NQ];
-  const unsigned short* Yh = reinterpret_cast<const unsigned short*>(g.Ylp);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int idx = head + 4 * q + t;
-    float w = 0.f, dv = 0.f;
-    unsigned short yb[NQ];
-#pragma unroll
-    for (int I = 0; I < NQ; ++I) yb[I] = 0;
-    if (idx < tail) {
-      const int s = ring_s[idx & 127];
-      w = (float)ring_w[idx & 127];
-      dv = (float)g.d[s];
-      const unsigned short* row = Yh + (size_t)s * KQ + col;
-#pragma unroll
-      for (int I = 0; I < NQ; ++I) yb[I] = row[16 * I];
-    }
 #pragma unroll
     for (int I = 0; I < NQ; ++I) {
-      const unsigned short ab = to_bf16(w * from_bf16(yb[I]));
+      const unsigned short ab = to_bf16(st.w[t] * from_bf16(st.y[t][I]));
       A[I][t] = (short)ab;
-      B[I][t] = (short)yb[I];
-      acc.bacc[I] = fmaf(from_bf16(ab), dv, acc.bacc[I]);
+      B[I][t] = (short)st.y[t][I];
+      acc.bacc[I] = fmaf(from_bf16(ab), st.dv[t], acc.bacc[I]);
     }
   }
   int blk = 0;
@@ -149,15 +131,48 @@ __device__ __forceinline__ void gram_step_bf16(GramAccLp<KQ, 2>& acc, const Gram
   }
 }
 
+// Every full step in the ring, pipelined as in the FP64 kernel: ring entries
+// two steps ahead, dy rows one step ahead, MFMAs of the current step.
+template <int KQ, int PREC>
+__device__ __forceinline__ void gram_drain_lp(GramAccLp<KQ, PREC>& acc, const GramArgs& g,
+                                              const int* ring_s, const double* ring_w, int& head,
+                                              int tail) {
+  constexpr int R = PREC == 1 ? 1 : 4;
+  constexpr int STEP = 4 * R;
+  typedef typename std::conditional<PREC == 1, float, unsigned short>::type E;
+  const int n = (tail - head) / STEP;
+  if (n == 0) return;
+  GramStepLp<KQ, R, E> sa = gram_load_lp<KQ, R, E>(g, ring_refs<R>(ring_s, ring_w, head, tail)), sb;
+  RingRefs<R> ra = ring_refs<R>(ring_s, ring_w, head + STEP, tail), rb;
+  for (int i = 0; i + 1 < n; i += 2) {
+    sb = gram_load_lp<KQ, R, E>(g, ra);
+    rb = ring_refs<R>(ring_s, ring_w, head + 2 * STEP, tail);
+    __builtin_amdgcn_sched_barrier(0);
+    gram_accumulate_lp<KQ>(acc, sa);
+    head += STEP;
+    sa = gram_load_lp<KQ, R, E>(g, rb);
+    ra = ring_refs<R>(ring_s, ring_w, head + 2 * STEP, tail);
+    __builtin_amdgcn_sched_barrier(0);
+    gram_accumulate_lp<KQ>(acc, sb);
+    head += STEP;
+  }
+  if (n & 1) {
+    gram_accumulate_lp<KQ>(acc, sa);
+    head += STEP;
+  }
+}
+
 template <int KQ, int PREC>
 __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* ring_s,
                                               double* ring_w) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
-  constexpr int STEP = PREC == 1 ? 4 : 16;
+  constexpr int R = PREC == 1 ? 1 : 4;
+  typedef typename std::conditional<PREC == 1, float, unsigned short>::type E;
   const int lane = lane_id();
-  const int gidx = bm.g0 + pl;
-  const int prob = find_problem(bm.prefix, bm.nprob, gidx);
+  // the point is the wavefront's: uniform (scalar registers and loads)
+  const int gidx = __builtin_amdgcn_readfirstlane(bm.g0 + pl);
+  const int prob = __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx));
   const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];
@@ -169,58 +184,32 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
 #pragma unroll
   for (int I = 0; I < NQ; ++I) acc.bacc[I] = 0.f;
 
-  int xlo[2], xhi[2], ylo[2], yhi[2];
-  const int nxi = cell_intervals_lp(x, g.R, g.nx, g.cb, g.ncx, xlo, xhi);
-  const int nyi = cell_intervals_lp(y, g.R, g.ny, g.cb, g.ncy, ylo, yhi);
+  ring_s[lane] = 0;
+  ring_s[lane + 64] = 0;
+  ring_w[lane] = 0.0;
+  ring_w[lane + 64] = 0.0;
+  wave_lds_sync();
+
+  WindowCursor cur;
+  bool ok = window_begin(cur, g, x, y);
+  Candidate cand{0, 0, 0.0};
+  if (ok) cand = load_candidate(g, cur.s, cur.s1);
   int head = 0, tail = 0;
-  for (int yi = 0; yi < nyi; ++yi) {
-    for (int cy = ylo[yi]; cy <= yhi[yi]; ++cy) {
-      for (int xi = 0; xi < nxi; ++xi) {
-        const int s0 = g.cell_start[cy * g.ncx + xlo[xi]];
-        const int s1 = g.cell_start[cy * g.ncx + xhi[xi] + 1];
-        for (int base = s0; base < s1; base += 64) {
-          const int s = base + lane;
-          double w = 0.0;
-          if (s < s1) {
-            int dx = abs(x - g.ox[s]);
-            dx = min(dx, g.nx - dx);
-            int dy = abs(y - g.oy[s]);
-            dy = min(dy, g.ny - dy);
-            const double r2d = (double)(dx * dx + dy * dy);
-            const double rv = g.rinv[s];
-            if (rv > 0.0 && r2d <= g.cut2) {
-              const double gl = g.loc == 0 ? exp(-r2d * g.inv2L2)
-                                           : (g.loc == 1 ? gc_weight(sqrt(r2d), g.invL) : 1.0);
-              w = gl * rv;
-            }
-          }
-          const bool in = w > 0.0;
-          const uint64_t mask = __ballot(in);
-          const int pos = __popcll(mask & ((1ull << lane) - 1ull));
-          if (in) {
-            ring_s[(tail + pos) & 127] = s;
-            ring_w[(tail + pos) & 127] = w;
-          }
-          tail += __popcll(mask);
-          wave_lds_sync();
-          while (tail - head >= STEP) {
-            if constexpr (PREC == 1)
-              gram_step_f32<KQ>(acc, g, ring_s, ring_w, head, tail);
-            else
-              gram_step_bf16<KQ>(acc, g, ring_s, ring_w, head, tail);
-            head += STEP;
-          }
-          wave_lds_sync();
-        }
-      }
-    }
+  while (ok) {
+    const int s = cur.s + lane;
+    const double w = candidate_weight(cand, g, x, y, s < cur.s1);
+    WindowCursor nx = cur;
+    const bool ok2 = window_next_batch(nx, g);
+    cand = ok2 ? load_candidate(g, nx.s, nx.s1) : load_candidate(g, cur.s, cur.s1);
+    tail = ring_append(ring_s, ring_w, tail, s, w);
+    wave_lds_sync();
+    gram_drain_lp<KQ, PREC>(acc, g, ring_s, ring_w, head, tail);
+    wave_lds_sync();
+    cur = nx;
+    ok = ok2;
   }
-  if (tail > head) {
-    if constexpr (PREC == 1)
-      gram_step_f32<KQ>(acc, g, ring_s, ring_w, head, tail);
-    else
-      gram_step_bf16<KQ>(acc, g, ring_s, ring_w, head, tail);
-  }
+  if (tail > head)
+    gram_accumulate_lp<KQ>(acc, gram_load_lp<KQ, R, E>(g, ring_refs<R>(ring_s, ring_w, head, tail)));
 
 #pragma unroll
   for (int I = 0; I < NQ; ++I) {
@@ -241,8 +230,8 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
 // Grid and persistent forms, as for k_gram_f64.
 template <int KQ, int PREC, bool PERSIST>
 __global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
-  __shared__ int s_ring[4][128];
-  __shared__ double w_ring[4][128];
+  __shared__ int s_ring[4][kRing];
+  __shared__ double w_ring[4][kRing];
   const int wid = threadIdx.x >> 6;
   if constexpr (!PERSIST) {
     const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
