@@ -44,8 +44,8 @@ struct DcLds {
     double zh[KP];  // recomputed weights zhat
   };
   double ds[KP];    // poles sorted ascending
-  // non-deflated (pole, weight) pairs, ascending, per block of S slots: slots
-  // [2a, 2a + K) and again [2a + K, 2a + 2K), so that a walk over the K - 2
+  // non-deflated (pole, squared weight) pairs, ascending, per block of S slots:
+  // slots [2a, 2a + K) and again [2a + K, 2a + 2K), so that a walk over the K - 2
   // poles away from a root, starting just above it and wrapping around,
   // reads consecutive slots
   alignas(16) double2 dw[2 * KP];
@@ -53,33 +53,19 @@ struct DcLds {
   double rs[KP];    //                       sine
   int pm[KP];       // sorted position -> block-local original index
   int inv[KP];      // sorted position -> non-deflated index, -1 if deflated
-  int rw[KP];       // non-deflated index -> block-local row of its eigenvector entry
+  int rw[KP];       // non-deflated index -> block-local row of its eigenvector
+                    // entry (kRowMask), kNegWeight set when its weight is negative
   // deflation rotations: first | second sorted position << 8; slot S - 1 of
   // a block (never a rotation: a block of S poles has at most S - 2) holds
   // the block's rotation count
   int rot[KP];
 };
 
+constexpr int kRowMask = 0xFF;
+constexpr int kNegWeight = 0x100;
+
 constexpr double kDcEps = 0x1p-52;
 constexpr int kSecularMaxIts = 64;   // room for a full bisection to 2 ulps
-
-// The root of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  (p1 < p2, B1, B2 >= 0: the
-// function rises from -inf to +inf between the poles) that lies in the
-// bracket (lo, hi) inside (p1, p2); NaN if neither root of the quadratic
-// does.  (With a tiny B the quadratic's other root sits just outside a pole
-// and can round to inside it, so the pole interval cannot pick the root.)
-__device__ __forceinline__ double two_pole_root(double c0, double B1, double B2, double p1,
-                                                double p2, double lo, double hi) {
-  const double a = c0;
-  const double b = -(c0 * (p1 + p2) + B1 + B2);
-  const double c = c0 * p1 * p2 + B1 * p2 + B2 * p1;
-  if (a == 0.0) return c / -b;
-  const double disc = fmax(b * b - 4.0 * a * c, 0.0);
-  const double q = -0.5 * (b + (b >= 0.0 ? sqrt(disc) : -sqrt(disc)));
-  const double r1 = q / a;
-  const double r2 = q != 0.0 ? c / q : __builtin_nan("");
-  return (r1 > lo && r1 < hi) ? r1 : r2;
-}
 
 // 1/x for finite x != 0 of moderate size: hardware estimate and two
 // Newton-Raphson steps.
@@ -91,8 +77,29 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(y, e, y);
 }
 
+// The root of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  (p1 < p2, B1, B2 >= 0: the
+// function rises from -inf to +inf between the poles) that lies in the
+// bracket (lo, hi) inside (p1, p2); NaN if neither root of the quadratic
+// does.  (With a tiny B the quadratic's other root sits just outside a pole
+// and can round to inside it, so the pole interval cannot pick the root.)
+__device__ __forceinline__ double two_pole_root(double c0, double B1, double B2, double p1,
+                                                double p2, double lo, double hi) {
+  const double a = c0;
+  const double b = -(c0 * (p1 + p2) + B1 + B2);
+  const double c = c0 * p1 * p2 + B1 * p2 + B2 * p1;
+  // (reciprocals to about an ulp: the result is a model step, checked
+  // against the bracket and verified by the next evaluation of f)
+  if (a == 0.0) return -c * frcp(b);
+  const double disc = fmax(b * b - 4.0 * a * c, 0.0);
+  const double q = -0.5 * (b + (b >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+  const double r1 = q * frcp(a);
+  const double r2 = q != 0.0 ? c * frcp(q) : __builtin_nan("");
+  return (r1 > lo && r1 < hi) ? r1 : r2;
+}
+
+
 // Root i (0-based) of f(lambda) = 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over
-// the K pairs dw[j] = (d_j, w_j) (LDS, d ascending, w_j != 0, rho > 0; slots
+// the K pairs dw[j] = (d_j, w_j^2) (LDS, d ascending, w_j != 0, rho > 0; slots
 // K .. 2K-1 repeat slots 0 .. K-1).  Returns the origin pole index with
 // lambda = d[org] + tau_out; conv is cleared if the iteration limit was hit.
 //
@@ -112,7 +119,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
   const double di1 = last ? di : dw[i + 1].x;
   double s2 = 0.0;
 #pragma unroll 8
-  for (int j = 0; j < K; ++j) s2 = fma(dw[j].y, dw[j].y, s2);
+  for (int j = 0; j < K; ++j) s2 += dw[j].y;
   // probe point: the interval midpoint (last root: halfway to d + rho |w|^2),
   // evaluated in coordinates shifted to d_i (d_j - d_i is exact for the
   // nearby poles, d_j - (d_i + half) would not be when the gap is tiny)
@@ -122,7 +129,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
 #pragma unroll 8
   for (int j = 0; j < K; ++j) {
     const double2 p = dw[j];
-    const double t = p.y * p.y * frcp((p.x - di) - half);
+    const double t = p.y * frcp((p.x - di) - half);
     fm += t;
     ti = j == i ? t : ti;
     ti1 = j == i + 1 ? t : ti1;
@@ -148,21 +155,21 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
   const double dorg = last || fm >= 0.0 ? di : di1;
   const double pi = di - dorg, pi1 = di1 - dorg;
   const double pm1 = i > 0 ? dw[i - 1].x - dorg : 0.0;
-  const double wi2 = dw[i].y * dw[i].y;
-  const double wi12 = last ? 0.0 : dw[i + 1].y * dw[i + 1].y;
+  const double wi2 = dw[i].y;
+  const double wi12 = last ? 0.0 : dw[i + 1].y;
   // start: the nearest poles exact, the other terms frozen at the probe point
   double tau;
   {
     const double tm = fm >= 0.0 || last ? half : -half;   // the probe, shifted to the origin
     const double rest = fm - ti - ti1;
-    const double t0 = last ? (rest > 0.0 ? pi + wi2 / rest : __builtin_nan(""))
+    const double t0 = last ? (rest > 0.0 ? pi + wi2 * frcp(rest) : __builtin_nan(""))
                            : two_pole_root(rest, wi2, wi12, pi, pi1, lo, hi);
     tau = (t0 > lo && t0 < hi) ? t0 : tm;
   }
   const int e1 = last ? i - 1 : i;           // -1 when K == 1
   const int e2 = last ? i : i + 1;
   const double P1 = last ? pm1 : pi, P2 = last ? pi : pi1;
-  const double W1 = e1 >= 0 ? dw[e1].y * dw[e1].y : 0.0, W2 = dw[e2].y * dw[e2].y;
+  const double W1 = e1 >= 0 ? dw[e1].y : 0.0, W2 = dw[e2].y;
   // the far poles: e2 + 1, .., K - 1, 0, .., e1 - 1 (the same count on every
   // lane of the block, so the lanes' loops stay in step)
   const double2* far = dw + e2 + 1;
@@ -178,7 +185,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
       const double2 p = far[o], q = far[o + 1];
       const double r0 = frcp((p.x - dorg) - tau);
       const double r1 = frcp((q.x - dorg) - tau);
-      const double t0 = p.y * p.y * r0, t1 = q.y * q.y * r1;
+      const double t0 = p.y * r0, t1 = q.y * r1;
       const double u0 = t0 * r0, u1 = t1 * r1;
       F0 += t0;
       A0 += fabs(t0);
@@ -192,7 +199,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
     if (o < nfar) {
       const double2 p = far[o];
       const double r0 = frcp((p.x - dorg) - tau);
-      const double t0 = p.y * p.y * r0;
+      const double t0 = p.y * r0;
       const double u0 = t0 * r0;
       F0 += t0;
       A0 += fabs(t0);
@@ -232,7 +239,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
     if (!last) {
       tn = two_pole_root(c0, B1, B2, P1, P2, lo, hi);
     } else if (K == 1) {
-      tn = c0 > 0.0 ? P2 + B2 / c0 : __builtin_nan("");
+      tn = c0 > 0.0 ? P2 + B2 * frcp(c0) : __builtin_nan("");
     } else {
       // last root: above both model poles, the larger root of the quadratic
       tn = __builtin_nan("");
@@ -241,7 +248,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
         const double cc = c0 * P1 * P2 + B1 * P2 + B2 * P1;
         const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
         const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
-        const double r1 = q / aa, r2 = q != 0.0 ? cc / q : r1;
+        const double r1 = q * frcp(aa), r2 = q != 0.0 ? cc * frcp(q) : r1;
         tn = fmax(r1, r2);
       }
     }
@@ -374,8 +381,9 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
   const int kidx = __popcll(kmask & ((1ull << t) - 1ull));
   if (keep) {
     L.inv[a + t] = kidx;
-    L.rw[a + kidx] = L.pm[a + t];
-    const double2 pr = make_double2(L.ds[a + t], L.ws[a + t]);
+    const double wv = L.ws[a + t];
+    L.rw[a + kidx] = L.pm[a + t] | (wv < 0.0 ? kNegWeight : 0);
+    const double2 pr = make_double2(L.ds[a + t], wv * wv);
     L.dw[2 * a + kidx] = pr;
     L.dw[2 * a + K + kidx] = pr;
   }
@@ -402,12 +410,14 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
       }
     }
     const double zr = sqrt(fmax(prod, 0.0));
-    L.zh[a + t] = L.dw[2 * a + t].y >= 0.0 ? zr : -zr;
+    L.zh[a + t] = (L.rw[a + t] & kNegWeight) ? -zr : zr;
   }
   if (t >= K) L.zh[a + t] = 0.0;
   wave_lds_sync();
-  // column t of the merge matrix (sorted eigenvalue order; rows block-local)
-  double lam_new;
+  // column t of the merge matrix (sorted eigenvalue order; rows block-local),
+  // left unnormalized: its scale cs goes to the padding column of row t and
+  // is applied to the merged rows below (the rotations commute with it)
+  double lam_new, cs = 1.0;
 #pragma unroll 8
   for (int r = 0; r < S; ++r) Wb[r * WS + t] = 0.0;
   if (trivial) {
@@ -426,11 +436,9 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
       for (int u = 0; u < K; ++u) {
         const double v = L.zh[a + u] * frcp((L.dw[2 * a + u].x - dorg) - tau);
         nrm = fma(v, v, nrm);
-        Wb[L.rw[a + u] * WS + t] = v;
+        Wb[(L.rw[a + u] & kRowMask) * WS + t] = v;
       }
-      const double inrm = 1.0 / sqrt(nrm);
-#pragma unroll 8
-      for (int u = 0; u < K; ++u) Wb[L.rw[a + u] * WS + t] *= inrm;
+      cs = 1.0 / sqrt(nrm);
       lam_new = dorg + tau;
     }
     // deflation rotations, last first, on rows pm[p], pm[j] of this column
@@ -445,6 +453,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
       Wb[rji] = fma(-sn, xp, c * xj);
     }
   }
+  Wb[t * WS + S] = cs;
   lam = flip ? -lam_new : lam_new;
   wave_lds_sync();
   // this lane's row of the merged block's eigenvector matrix
@@ -460,7 +469,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
     for (int c = 0; c < S; ++c) out[c] = fma(x, Wr[c], out[c]);
   }
 #pragma unroll
-  for (int c = 0; c < S; ++c) qs[c] = out[c];
+  for (int c = 0; c < S; ++c) qs[c] = out[c] * Wb[c * WS + S];
   wave_lds_sync();
 }
 

@@ -203,16 +203,22 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
 //   d_j = T[j][j] -> sh.d,  e_j = T[j+1][j] -> sh.e,  tau_i -> sh.tau,
 //   a[i] = v_jj of step i for i < jj (the lane's entries of the reflectors).
-// Step I of the reduction (I is a compile-time index so that a[] stays in
-// registers at every size).
+// With p = tau A v and K = (tau/2) p.v the update A - v w^T - w v^T,
+// w = p - K v, is A - v p^T - (p - 2K v) v^T: p is broadcast as soon as it
+// is known and the reduction for K runs while it travels through LDS.
+// Column i+1 of the updated row (the next step's x) is updated first and the
+// next step's two column reductions (alpha, sigma) are started before the
+// rest of the row, so their latency hides behind it.
+// Step i of the reduction (a compile-time index so that a[] stays in
+// registers at every size); alpha = A[i+1][i] and sig = sum_{j>i+1} A[j][i]^2
+// come in from the step before and go out for the step after.
 template <int KP, int i>
-__device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
+__device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
+                                             double& alpha, double& sig) {
   const int so = opaque(seg * KP);
   double* vb = &sh.vb[0][0] + so;
-  double* wb = &sh.wb[0][0] + so;
+  double* pb = &sh.wb[0][0] + so;
   const double x = a[i];                                   // A[jj][i]
-  const double alpha = group_read<KP>(x, i + 1);            // A[i+1][i]
-  const double sig = group_sum<KP>(jj > i + 1 ? x * x : 0.0);
   const bool refl = sig != 0.0;                             // uniform per matrix
   const double nrm = sqrt(fma(alpha, alpha, sig));
   const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
@@ -221,53 +227,51 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
   vb[jj] = vj;
   wave_lds_sync();
+  constexpr int c0 = (i + 1) & ~1;
+  constexpr bool more = i + 1 < KP - 2;                     // a step follows
   if constexpr (KP <= 32) {
-    // the trailing parts of v and w go to registers in one burst of LDS
+    // the trailing parts of v and p go to registers in one burst of LDS
     // reads each (one wait per vector instead of one per few products)
-    constexpr int c0 = (i + 1) & ~1;
-    double vv[KP], ww[KP];
-#pragma unroll
-    for (int c = c0; c < KP; c += 2) {
-      const double2 t2 = *reinterpret_cast<const double2*>(vb + c);
-      vv[c] = t2.x;
-      vv[c + 1] = t2.y;
-    }
-    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+    double vv[KP], pp[KP];
+    load_pairs<KP, c0, KP>(vv, vb);
     double pc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = i + 1; c < KP; ++c) pc[c & 3] = fma(a[c], vv[c], pc[c & 3]);
     const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
+    pb[jj] = p;
     const double K = 0.5 * tau * group_sum<KP>(p * vj);
-    const double w = fma(-K, vj, p);
-    wb[jj] = w;
     wave_lds_sync();
-#pragma unroll
-    for (int c = c0; c < KP; c += 2) {
-      const double2 t2 = *reinterpret_cast<const double2*>(wb + c);
-      ww[c] = t2.x;
-      ww[c + 1] = t2.y;
+    load_pairs<KP, c0, KP>(pp, pb);
+    const double wj = fma(-2.0 * K, vj, p);
+    a[i + 1] = fma(-wj, vv[i + 1], fma(-vj, pp[i + 1], a[i + 1]));
+    if constexpr (more) {
+      alpha = group_read<KP>(a[i + 1], i + 2);
+      sig = group_sum<KP>(jj > i + 2 ? a[i + 1] * a[i + 1] : 0.0);
     }
-    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0)
 #pragma unroll
-    for (int c = i + 1; c < KP; ++c) a[c] = fma(-w, vv[c], fma(-vj, ww[c], a[c]));
+    for (int c = i + 2; c < KP; ++c) a[c] = fma(-wj, vv[c], fma(-vj, pp[c], a[c]));
   } else {
-    constexpr int c0 = (i + 1) & ~1;
-    double vv[KP], ww[KP];
-    // p = tau A v over the trailing block, w = p - (tau/2)(p.v) v
+    double vv[KP], pp[KP];
     constexpr int CH = 16;
     load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, vb);
     double pc[4] = {0.0, 0.0, 0.0, 0.0};
     dot_stream<KP, i + 1, c0, CH>(a, vb, vv, pc);
     const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
+    pb[jj] = p;
     const double K = 0.5 * tau * group_sum<KP>(p * vj);
-    const double w = fma(-K, vj, p);
-    wb[jj] = w;
     wave_lds_sync();
-    // A <- A - v w^T - w v^T on rows/columns > i (rows <= i have v = w = 0)
+    const double wj = fma(-2.0 * K, vj, p);
+    const double v1 = vb[i + 1], p1 = pb[i + 1];
+    a[i + 1] = fma(-wj, v1, fma(-vj, p1, a[i + 1]));
+    if constexpr (more) {
+      alpha = group_read<KP>(a[i + 1], i + 2);
+      sig = group_sum<KP>(jj > i + 2 ? a[i + 1] * a[i + 1] : 0.0);
+    }
     constexpr int CH2 = 8;
-    load_pairs<KP, c0, cmin(c0 + CH2, KP)>(vv, vb);
-    load_pairs<KP, c0, cmin(c0 + CH2, KP)>(ww, wb);
-    rank2_stream<KP, i + 1, c0, CH2>(a, vb, wb, vv, ww, vj, w);
+    constexpr int c2 = (i + 2) & ~1;
+    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(vv, vb);
+    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(pp, pb);
+    rank2_stream<KP, i + 2, c2, CH2>(a, vb, pb, vv, pp, vj, wj);
   }
   // nothing of the next step may be scheduled into this one (the
   // interleaving would keep two copies of the row live)
@@ -283,7 +287,9 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
 template <int KP, int... Is>
 __device__ __forceinline__ void tridiag_steps(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
                                               std::integer_sequence<int, Is...>) {
-  (tridiag_step<KP, Is>(a, sh, seg, jj), ...);
+  double alpha = group_read<KP>(a[0], 1);
+  double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
+  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig), ...);
 }
 
 template <int KP>
