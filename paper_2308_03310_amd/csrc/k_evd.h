@@ -444,9 +444,9 @@ __device__ __forceinline__ void write_eig(const EvdArgs& e, const double* M, int
 }
 
 // Mode 0: transform and in-place update of the point's nine components,
-// from V (natural layout in M, row stride KP+1), this lane's eigenvalue lam
-// and this lane's entry of b.  Row reads M[jj][c] and column reads M[m][jj] are both
-// bank-conflict free within 16-lane groups.
+// from V (rows from the natural layout in M, row stride KP+1, bank-conflict
+// free; this lane's column jj from q[]), this lane's eigenvalue lam and this
+// lane's entry of b.
 // T = double: FP64 contractions.  T = float: the reduced-precision forms —
 // V, b, dX, U and the weights are rounded to FP32 or BF16 (e.prec) as
 // contraction operands and accumulated in FP32; the ensemble mean, its
@@ -460,7 +460,8 @@ __device__ __forceinline__ float opnd<float>(double x, int prec) { return round_
 
 template <int KP, typename T>
 __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
-                                                 int pl, bool valid, double lam, double bj) {
+                                                 int pl, bool valid, double lam, double bj,
+                                                 const double (&q)[KP]) {
   const int prec = e.prec;
   constexpr int S = KP + 1;
   const int k = e.k;
@@ -470,9 +471,10 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
   double* bz = sh.dxu[seg][0];
   bz[jj] = bj;
   wave_lds_sync();
+  // (column jj of V is this lane's q[] from the back-transformation)
   T z = 0;
-#pragma unroll 4
-  for (int r = 0; r < KP; ++r) z = fma(opnd<T>(M[r * S + jj], prec), opnd<T>(bz[r], prec), z);
+#pragma unroll
+  for (int r = 0; r < KP; ++r) z = fma(opnd<T>(q[r], prec), opnd<T>(bz[r], prec), z);
   const double z1 = (double)z / lam;
   wave_lds_sync();
   bz[jj] = z1;
@@ -511,9 +513,9 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
     T U[CG];
 #pragma unroll
     for (int i = 0; i < CG; ++i) U[i] = 0;
-#pragma unroll 2
+#pragma unroll
     for (int m = 0; m < KP; ++m) {
-      const T vm = opnd<T>(M[m * S + jj], prec);
+      const T vm = opnd<T>(q[m], prec);
 #pragma unroll
       for (int i = 0; i < CG; ++i)
         if (i < nc) U[i] = fma((T)sh.dxu[seg][i][m], vm, U[i]);
@@ -598,9 +600,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
     return;
   }
   if (e.prec == 0)
-    transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam, bj);
+    transform_update<KP, double>(e, sh, seg, jj, pl, valid, lam, bj, q);
   else
-    transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam, bj);
+    transform_update<KP, float>(e, sh, seg, jj, pl, valid, lam, bj, q);
 }
 
 template <int KP>
