@@ -5,8 +5,10 @@
 //
 // Method (Cuppen 1981; Dongarra & Sorensen 1987; stable eigenvectors from
 // Gu & Eisenstat 1995):
-//   * T is torn at every coupling e_i, leaving 1 x 1 leaves d_i - e_{i-1} - e_i;
-//   * levels S = 2, 4, .., KP merge two children of size S/2 at the split
+//   * T is torn at every other coupling (a torn coupling e_i comes off the
+//     two diagonal entries next to it), leaving 2 x 2 leaves that one Jacobi
+//     rotation each diagonalizes;
+//   * levels S = 4, 8, .., KP merge two children of size S/2 at the split
 //     m = a + S/2:  T_block = diag(Q1 D1 Q1^T, Q2 D2 Q2^T) + beta u u^T with
 //     beta = e_{m-1}, u = e_{m-1} + e_m, so the block's eigenproblem is the
 //     rank-one update D + beta z z^T of the children's eigenvalues, with
@@ -15,7 +17,8 @@
 //     equal poles are deflated; every other eigenvalue is the root of the
 //     secular equation 1/rho + sum_j w_j^2 / (d_j - lambda) = 0 in its own
 //     pole interval, found by one lane with a two-pole rational model
-//     safeguarded by bisection, in the shifted form lambda = d_org + tau;
+//     (secular_root) safeguarded by bisection, in the shifted form
+//     lambda = d_org + tau;
 //   * the weights are recomputed from the roots (Loewner) so that the
 //     eigenvectors (D - lambda I)^-1 zhat are numerically orthogonal;
 //   * lane r keeps row r of the tridiagonal eigenvector matrix restricted to
@@ -98,6 +101,41 @@ __device__ __forceinline__ double two_pole_root(double c0, double B1, double B2,
 }
 
 
+// One model step of the secular iteration at the iterate t (origin-shifted):
+// the near terms W1/(P1 - x) + W2/(P2 - x) exact, the far sum (value F,
+// slope Fd, half curvature Fh at t) replaced by c + s1/(P1 - x) + s2/(P2 - x)
+// matched to it in value, slope and curvature (interior root) or in value
+// and slope on P1 alone (root above the last pole); returns the model's root
+// in (lo, hi), or NaN.
+__device__ __forceinline__ double secular_model_step(double irho, double F, double Fd, double Fh,
+                                                     double W1, double W2, double P1, double P2,
+                                                     double t, double lo, double hi, bool last,
+                                                     int K) {
+  const double g1 = P1 - t, g2 = P2 - t;
+  // split of F' over the model poles: a1 = s1/g1^2, a2 = s2/g2^2
+  double a1, a2;
+  if (last) {
+    a1 = Fd;
+    a2 = 0.0;
+  } else {
+    const double ig = frcp(g2 - g1);
+    a1 = fmax((Fh * g2 - Fd) * g1 * ig, 0.0);
+    a2 = fmax((Fd - Fh * g1) * g2 * ig, 0.0);
+  }
+  const double c0 = irho + F - a1 * g1 - a2 * g2;
+  const double B1 = W1 + a1 * g1 * g1, B2 = W2 + a2 * g2 * g2;
+  if (!last) return two_pole_root(c0, B1, B2, P1, P2, lo, hi);
+  if (K == 1) return c0 > 0.0 ? P2 + B2 * frcp(c0) : __builtin_nan("");
+  // root above both model poles: the larger root of the quadratic
+  if (!(c0 > 0.0)) return __builtin_nan("");
+  const double aa = c0, bb = -(c0 * (P1 + P2) + B1 + B2);
+  const double cc = c0 * P1 * P2 + B1 * P2 + B2 * P1;
+  const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
+  const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+  const double r1 = q * frcp(aa), r2 = q != 0.0 ? cc * frcp(q) : r1;
+  return fmax(r1, r2);
+}
+
 // Root i (0-based) of f(lambda) = 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over
 // the K pairs dw[j] = (d_j, w_j^2) (LDS, d ascending, w_j != 0, rho > 0; slots
 // K .. 2K-1 repeat slots 0 .. K-1).  Returns the origin pole index with
@@ -157,7 +195,10 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
   const double pm1 = i > 0 ? dw[i - 1].x - dorg : 0.0;
   const double wi2 = dw[i].y;
   const double wi12 = last ? 0.0 : dw[i + 1].y;
-  // start: the nearest poles exact, the other terms frozen at the probe point
+  // start: the nearest poles exact, the other terms frozen at their value at
+  // the probe (a model matched in slope and curvature there as well
+  // extrapolates badly to a root that hugs a pole, the common case with
+  // small weights)
   double tau;
   {
     const double tm = fm >= 0.0 || last ? half : -half;   // the probe, shifted to the origin
@@ -166,7 +207,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
                            : two_pole_root(rest, wi2, wi12, pi, pi1, lo, hi);
     tau = (t0 > lo && t0 < hi) ? t0 : tm;
   }
-  const int e1 = last ? i - 1 : i;           // -1 when K == 1
+  const int e1 = last ? i - 1 : i;           // the two poles nearest the root; -1 when K == 1
   const int e2 = last ? i : i + 1;
   const double P1 = last ? pm1 : pi, P2 = last ? pi : pi1;
   const double W1 = e1 >= 0 ? dw[e1].y : 0.0, W2 = dw[e2].y;
@@ -223,35 +264,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
       conv = true;
       break;
     }
-    // split of F' over the model poles: a1 = s1/g1^2, a2 = s2/g2^2
-    double a1, a2;
-    if (last) {
-      a1 = Fd;
-      a2 = 0.0;
-    } else {
-      const double ig = frcp(g2 - g1);
-      a1 = fmax((Fh * g2 - Fd) * g1 * ig, 0.0);
-      a2 = fmax((Fd - Fh * g1) * g2 * ig, 0.0);
-    }
-    const double c0 = irho + F - a1 * g1 - a2 * g2;
-    const double B1 = W1 + a1 * g1 * g1, B2 = W2 + a2 * g2 * g2;
-    double tn;
-    if (!last) {
-      tn = two_pole_root(c0, B1, B2, P1, P2, lo, hi);
-    } else if (K == 1) {
-      tn = c0 > 0.0 ? P2 + B2 * frcp(c0) : __builtin_nan("");
-    } else {
-      // last root: above both model poles, the larger root of the quadratic
-      tn = __builtin_nan("");
-      if (c0 > 0.0) {
-        const double aa = c0, bb = -(c0 * (P1 + P2) + B1 + B2);
-        const double cc = c0 * P1 * P2 + B1 * P2 + B2 * P1;
-        const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
-        const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
-        const double r1 = q * frcp(aa), r2 = q != 0.0 ? cc * frcp(q) : r1;
-        tn = fmax(r1, r2);
-      }
-    }
+    const double tn = secular_model_step(irho, F, Fd, Fh, W1, W2, P1, P2, tau, lo, hi, last, K);
     const bool inside = tn > lo && tn < hi;
     const double tnew = inside ? tn : 0.5 * (lo + hi);
     // a model step (not a bisection) this small has converged: the model
@@ -492,12 +505,31 @@ template <int KP>
 __device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], double& lam, DcLds<KP>& L,
                                                const double* d, const double* e, double* W, int jj,
                                                double deps) {
-  const double el = jj > 0 ? e[jj - 1] : 0.0;
-  lam = d[jj] - el - e[jj];                  // leaves after tearing every coupling
+  // Leaves of size 2: T torn at every other coupling, each 2 x 2 block
+  // [[d_a - e_{a-1}, e_a], [e_a, d_{a+1} - e_{a+1}]] diagonalized in closed
+  // form by one Jacobi rotation (Golub & Van Loan, sym.schur2): J^T A J =
+  // diag(A_00 - t e_a, A_11 + t e_a) with J = [[c, s], [-s, c]].
+  const int a = jj & ~1;
+  const double A0 = d[a] - (a > 0 ? e[a - 1] : 0.0);
+  const double A1 = d[a + 1] - e[a + 1];
+  const double b = e[a];
+  double c = 1.0, sn = 0.0, l0 = A0, l1 = A1;
+  if (b != 0.0) {
+    const double th = (A1 - A0) / (2.0 * b);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    sn = t * c;
+    l0 = fma(-t, b, A0);
+    l1 = fma(t, b, A1);
+  }
+  const bool top = jj == a;                  // row a: (c, s); row a + 1: (-s, c)
+  lam = top ? l0 : l1;                       // column 0 <-> l0, column 1 <-> l1
 #pragma unroll
-  for (int c = 0; c < KP; ++c) qs[c] = c == 0 ? 1.0 : 0.0;
+  for (int q = 0; q < KP; ++q) qs[q] = 0.0;
+  qs[0] = top ? c : -sn;
+  qs[1] = top ? sn : c;
   bool ok = true;
-  dc_levels<KP, 2>(qs, lam, L, e, W, jj, deps, ok);
+  dc_levels<KP, 4>(qs, lam, L, e, W, jj, deps, ok);
   return ok;
 }
 
