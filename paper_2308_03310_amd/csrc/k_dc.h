@@ -290,7 +290,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
 // matrix's LDS scratch for the merge matrices (KP * (KP + 1) doubles).
 template <int KP, int S>
 __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP>& L,
-                                         const double* e_orig, double* W, int jj, double deps,
+                                         double ej, double* W, int jj, double deps,
                                          bool& ok) {
   constexpr int H = S / 2;
   constexpr int WS = S + 1;                  // row stride of a block's merge matrix
@@ -308,7 +308,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
 #pragma unroll
     for (int q = 0; q < H; ++q) L.zb[m + q] = qs[q];
   }
-  const double beta = e_orig[m - 1];
+  const double beta = __shfl(ej, m - 1, KP);   // e_{m-1}, held by lane m - 1
   const bool flip = beta < 0.0;
   const double D = flip ? -lam : lam;
   L.dt[jj] = D;
@@ -488,31 +488,32 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
 
 template <int KP, int S>
 __device__ __forceinline__ void dc_levels(double (&qs)[KP], double& lam, DcLds<KP>& L,
-                                          const double* e_orig, double* W, int jj, double deps,
+                                          double ej, double* W, int jj, double deps,
                                           bool& ok) {
   if constexpr (S <= KP) {
-    dc_merge<KP, S>(qs, lam, L, e_orig, W, jj, deps, ok);
-    dc_levels<KP, 2 * S>(qs, lam, L, e_orig, W, jj, deps, ok);
+    dc_merge<KP, S>(qs, lam, L, ej, W, jj, deps, ok);
+    dc_levels<KP, 2 * S>(qs, lam, L, ej, W, jj, deps, ok);
   }
 }
 
-// Eigen-decomposition of the tridiagonal (d, e) (LDS, KP entries each; e
-// is not modified).  Deflation tolerance 8 deps max(|D|, rho) per merge, with
+// Eigen-decomposition of the tridiagonal (d, e), lane jj of the KP-lane group
+// holding dj = d_jj and ej = e_jj = T[jj+1][jj] (e_{KP-1} = 0).  Deflation tolerance 8 deps max(|D|, rho) per merge, with
 // deps the unit roundoff of the arithmetic that produced the matrix.  On
 // return lam is the eigenvalue of column jj and qs[] is row jj of the
 // eigenvector matrix.  Returns false if a secular root ran out of iterations.
 template <int KP>
 __device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], double& lam, DcLds<KP>& L,
-                                               const double* d, const double* e, double* W, int jj,
+                                               double dj, double ej, double* W, int jj,
                                                double deps) {
   // Leaves of size 2: T torn at every other coupling, each 2 x 2 block
   // [[d_a - e_{a-1}, e_a], [e_a, d_{a+1} - e_{a+1}]] diagonalized in closed
   // form by one Jacobi rotation (Golub & Van Loan, sym.schur2): J^T A J =
   // diag(A_00 - t e_a, A_11 + t e_a) with J = [[c, s], [-s, c]].
   const int a = jj & ~1;
-  const double A0 = d[a] - (a > 0 ? e[a - 1] : 0.0);
-  const double A1 = d[a + 1] - e[a + 1];
-  const double b = e[a];
+  const double em1 = __shfl(ej, a > 0 ? a - 1 : 0, KP);
+  const double A0 = __shfl(dj, a, KP) - (a > 0 ? em1 : 0.0);
+  const double A1 = __shfl(dj, a + 1, KP) - __shfl(ej, a + 1, KP);
+  const double b = __shfl(ej, a, KP);
   double c = 1.0, sn = 0.0, l0 = A0, l1 = A1;
   if (b != 0.0) {
     const double th = (A1 - A0) / (2.0 * b);
@@ -529,7 +530,7 @@ __device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], double& lam, Dc
   qs[0] = top ? c : -sn;
   qs[1] = top ? sn : c;
   bool ok = true;
-  dc_levels<KP, 4>(qs, lam, L, e, W, jj, deps, ok);
+  dc_levels<KP, 4>(qs, lam, L, ej, W, jj, deps, ok);
   return ok;
 }
 

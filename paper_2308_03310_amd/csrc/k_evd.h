@@ -39,14 +39,15 @@ namespace letkf {
 // (Lambda^-1 V^T b, then dX and dX V for up to five of the nine components at
 // a time).
 constexpr int kCompGroup = 5;
+
+#ifndef LETKF_REFL_REG_MAX
+#define LETKF_REFL_REG_MAX 32
+#endif
 template <int KP>
 struct EvdLds {
   static constexpr int G = 64 / KP;
   static constexpr int S = KP + 1;   // row stride: 16 consecutive rows hit distinct banks
   double mat[G][KP * S];
-  double d[G][KP];
-  double e[G][KP];
-  double tau[G][KP];
   union {
     struct {                         // tridiagonalization: broadcast vectors
       double vb[G][KP];
@@ -166,6 +167,22 @@ __device__ __forceinline__ void dot_stream(const double (&x)[KP], const double* 
   }
 }
 
+//   pc[c % 4] += x[c] v[c] for c in [LO, KP), nc[c % 4] += v[c]^2 for c in (LO, KP)
+template <int KP, int LO, int CS, int CH>
+__device__ __forceinline__ void dotn_stream(const double (&x)[KP], const double* vsrc,
+                                            double (&v)[KP], double (&pc)[4], double (&nc)[4]) {
+  if constexpr (CS < KP) {
+    constexpr int NS = CS + CH;
+    if constexpr (NS < KP) load_pairs<KP, NS, cmin(NS + CH, KP)>(v, vsrc);
+#pragma unroll
+    for (int c = cmax(CS, LO); c < cmin(NS, KP); ++c) pc[c & 3] = fma(x[c], v[c], pc[c & 3]);
+#pragma unroll
+    for (int c = cmax(CS, LO + 1); c < cmin(NS, KP); ++c) nc[c & 3] = fma(v[c], v[c], nc[c & 3]);
+    __builtin_amdgcn_sched_barrier(0);
+    dotn_stream<KP, LO, NS, CH>(x, vsrc, v, pc, nc);
+  }
+}
+
 //   x[c] -= f v[c] for c in [LO, KP)
 template <int KP, int LO, int CS, int CH>
 __device__ __forceinline__ void axpy_stream(double (&x)[KP], const double* vsrc, double (&v)[KP],
@@ -201,7 +218,7 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // Householder tridiagonalization of the symmetric matrix whose row jj this
 // lane holds in a[].  Step i annihilates A[i+2:, i] with H_i = I - tau v v^T,
 // v = (0,..,0, 1, v_{i+2}, .., v_{n-1}); afterwards
-//   d_j = T[j][j] -> sh.d,  e_j = T[j+1][j] -> sh.e,  tau_i -> sh.tau,
+//   d_j = T[j][j] and e_j = T[j+1][j] in registers of lane j (dj, ej),
 //   a[i] = v_jj of step i for i < jj (the lane's entries of the reflectors).
 // With p = tau A v and K = (tau/2) p.v the update A - v w^T - w v^T,
 // w = p - K v, is A - v p^T - (p - 2K v) v^T: p is broadcast as soon as it
@@ -214,7 +231,7 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // come in from the step before and go out for the step after.
 template <int KP, int i>
 __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
-                                             double& alpha, double& sig) {
+                                             double& alpha, double& sig, double& ej) {
   const int so = opaque(seg * KP);
   double* vb = &sh.vb[0][0] + so;
   double* pb = &sh.wb[0][0] + so;
@@ -278,31 +295,39 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   __builtin_amdgcn_sched_barrier(0);
   wave_lds_sync();
   if (jj > i) a[i] = vj;
-  if (jj == i) {
-    sh.e[seg][i] = beta;
-    sh.tau[seg][i] = tau;
-  }
+  if (jj == i) ej = beta;
 }
 
 template <int KP, int... Is>
 __device__ __forceinline__ void tridiag_steps(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
+                                              double& ej,
                                               std::integer_sequence<int, Is...>) {
   double alpha = group_read<KP>(a[0], 1);
   double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
-  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig), ...);
+  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig, ej), ...);
 }
 
+// The reduction; lane jj ends with dj = T[jj][jj] and ej = T[jj+1][jj]
+// (e_{KP-1} = 0).  The reflectors' tau values are not kept: the
+// back-transformation recovers each from its vector (tau = 2 / v^T v).
 template <int KP>
-__device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj) {
-  tridiag_steps<KP>(a, sh, seg, jj, std::make_integer_sequence<int, KP - 2>{});
+__device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
+                                               double& dj, double& ej) {
+  ej = 0.0;
+  tridiag_steps<KP>(a, sh, seg, jj, ej, std::make_integer_sequence<int, KP - 2>{});
   double dg = 0.0;
 #pragma unroll
   for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;
-  sh.d[seg][jj] = dg;
-  if (jj == KP - 2) sh.e[seg][KP - 2] = a[KP - 1];
-  if (jj == KP - 1) sh.e[seg][KP - 1] = 0.0;
+  dj = dg;
+  if (jj == KP - 2) ej = a[KP - 1];
   wave_lds_sync();
 }
+
+// Whether the Householder vectors stay in registers (a[]) through the divide
+// and conquer; beyond that size they wait in global scratch, which leaves
+// the registers to the merges.
+template <int KP>
+constexpr bool kReflInRegisters = KP <= LETKF_REFL_REG_MAX;
 
 // Packed position of reflector i's entry on row r (0 <= i < r < k): the
 // reflectors' entries below their unit element, reflector by reflector.
@@ -334,27 +359,32 @@ __device__ __forceinline__ void load_reflector(double (&v)[KP], const double* ro
   }
 }
 
+// tau of a Householder vector v (v_{i+1} = 1) from s = sum_{r > i+1} v_r^2:
+// the reduction's tau = (beta - alpha) / beta equals 2 / v^T v = 2 / (1 + s),
+// and a step that reflected nothing has v = e_{i+1} (s = 0) and tau = 0.
+// (s is summed apart from the unit entry: 1 + s rounds to 1 long before the
+// reflection becomes negligible, when it is close to a sign flip, tau = 2.)
+__device__ __forceinline__ double tau_of(double s) { return s > 0.0 ? 2.0 * frcp(1.0 + s) : 0.0; }
+
 // H_i applied to this lane's column q, the reflector streamed from LDS (KP = 64).
 template <int KP, int i>
-__device__ __forceinline__ void apply_reflector_stream(double (&q)[KP], const double* rows,
-                                                       const double* taus) {
+__device__ __forceinline__ void apply_reflector_stream(double (&q)[KP], const double* rows) {
   constexpr int c0 = (i + 1) & ~1;
   constexpr int CH = 16;
   const double* v = rows + i * KP;
   double vv[KP];
   load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, v);
-  double pc[4] = {0.0, 0.0, 0.0, 0.0};
-  dot_stream<KP, i + 1, c0, CH>(q, v, vv, pc);
-  const double f = taus[i] * ((pc[0] + pc[1]) + (pc[2] + pc[3]));
+  double pc[4] = {0.0, 0.0, 0.0, 0.0}, nc[4] = {0.0, 0.0, 0.0, 0.0};
+  dotn_stream<KP, i + 1, c0, CH>(q, v, vv, pc, nc);
+  const double f = tau_of((nc[0] + nc[1]) + (nc[2] + nc[3])) * ((pc[0] + pc[1]) + (pc[2] + pc[3]));
   load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, v);
   axpy_stream<KP, i + 1, c0, CH>(q, v, vv, f);
 }
 
 template <int KP, int... Is>
 __device__ __forceinline__ void apply_reflectors_stream(double (&q)[KP], const double* rows,
-                                                        const double* taus,
                                                         std::integer_sequence<int, Is...>) {
-  (apply_reflector_stream<KP, KP - 3 - Is>(q, rows, taus), ...);
+  (apply_reflector_stream<KP, KP - 3 - Is>(q, rows), ...);
 }
 
 // H_i .. H_0 applied to this lane's column q (KP <= 32), reflector i taken
@@ -362,21 +392,21 @@ __device__ __forceinline__ void apply_reflectors_stream(double (&q)[KP], const d
 // LDS latency of a reflector hides behind the products of the one before.
 template <int KP, int i>
 __device__ __forceinline__ void apply_reflectors_pipelined(double (&q)[KP], double (&cur)[KP],
-                                                           const double* rows,
-                                                           const double* taus) {
+                                                           const double* rows) {
   double nxt[KP];
   if constexpr (i > 0) load_reflector<KP, i - 1>(nxt, rows);
-  const double t = taus[i];
-  double dc[4] = {0.0, 0.0, 0.0, 0.0};
+  double dc[4] = {0.0, 0.0, 0.0, 0.0}, nc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = i + 1; r < KP; ++r) dc[r & 3] = fma(q[r], cur[r], dc[r & 3]);
-  const double f = t * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
+#pragma unroll
+  for (int r = i + 2; r < KP; ++r) nc[r & 3] = fma(cur[r], cur[r], nc[r & 3]);
+  const double f = tau_of((nc[0] + nc[1]) + (nc[2] + nc[3])) * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
 #pragma unroll
   for (int r = i + 1; r < KP; ++r) q[r] = fma(-f, cur[r], q[r]);
   // no instruction of the next reflector ahead of this point (it would keep
   // a third reflector's registers live)
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (i > 0) apply_reflectors_pipelined<KP, i - 1>(q, nxt, rows, taus);
+  if constexpr (i > 0) apply_reflectors_pipelined<KP, i - 1>(q, nxt, rows);
 }
 
 // V = H Q_T with H = H_0 H_1 .. H_{n-3}: q holds row jj of Q_T on entry.
@@ -398,7 +428,7 @@ __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a
 #pragma unroll
   for (int r = 0; r < KP; ++r) q[r] = M[r * S + jj];
   wave_lds_sync();
-  if constexpr (KP <= 32) {
+  if constexpr (kReflInRegisters<KP>) {
 #pragma unroll
     for (int i = 0; i < KP - 2; ++i) M[i * KP + jj] = jj > i ? a[i] : 0.0;
   } else {
@@ -413,10 +443,10 @@ __device__ __forceinline__ void back_transform(double (&q)[KP], const double (&a
     const double* rows = &sh.mat[0][0] + opaque(seg * KP * (KP + 1));
     double cur[KP];
     load_reflector<KP, KP - 3>(cur, rows);
-    apply_reflectors_pipelined<KP, KP - 3>(q, cur, rows, sh.tau[seg]);
+    apply_reflectors_pipelined<KP, KP - 3>(q, cur, rows);
   } else {
     const double* rows = &sh.mat[0][0] + opaque(seg * KP * (KP + 1));
-    apply_reflectors_stream<KP>(q, rows, sh.tau[seg], std::make_integer_sequence<int, KP - 2>{});
+    apply_reflectors_stream<KP>(q, rows, std::make_integer_sequence<int, KP - 2>{});
   }
   wave_lds_sync();
 #pragma unroll
@@ -576,19 +606,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   double bj = 0.0;
   stage_matrix<KP>(e, sh, seg, jj, pl, valid, bj);
   wave_lds_sync();
-  // KP = 64: scratch for the reflectors during the divide and conquer: this
-  // point's Gram output (mode 0, consumed by the staging above) or its
-  // eigenvector output (mode 1, written last)
+  // Scratch for the reflectors when they do not stay in registers through
+  // the divide and conquer: this point's Gram output (mode 0, consumed by the
+  // staging above) or its eigenvector output (mode 1, written last).
   double* rv = e.mode == 0 ? e.C + (size_t)pl * ((KP / 16) * (KP / 16 + 1) / 2) * 256 : e.vec + (size_t)pl * e.k * e.k;
   double a[KP];
   load_rows<KP>(sh.mat[seg], jj, a);
   wave_lds_sync();
-  tridiagonalize<KP>(a, sh, seg, jj);
-  if constexpr (KP > 32) store_reflectors<KP>(a, rv, e.k, jj, valid);
+  double dj, ej;   // this lane's diagonal and coupling of T
+  tridiagonalize<KP>(a, sh, seg, jj, dj, ej);
+  if constexpr (!kReflInRegisters<KP>) store_reflectors<KP>(a, rv, e.k, jj, valid);
+
   double q[KP];
   double lam;
   const bool conv =
-      dc_tridiagonal<KP>(q, lam, sh.dc[seg], sh.d[seg], sh.e[seg], sh.mat[seg], jj, e.defl_eps);
+      dc_tridiagonal<KP>(q, lam, sh.dc[seg], dj, ej, sh.mat[seg], jj, e.defl_eps);
   // any lane of the matrix whose secular root ran out of iterations
   const uint64_t segmask = KP == 64 ? ~0ull : (((1ull << KP) - 1ull) << (seg * KP));
   const bool all_conv = (__ballot(!conv) & segmask) == 0;
