@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -21,6 +22,7 @@ SOURCES = ["k_evd64.hip", "k_evd32.hip", "k_evd16.hip", "k_gram.hip", "k_gram_lp
            "k_lbm.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+MAX_SCRATCH = 256   # bytes of private memory per lane a kernel may use
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions in any device code
@@ -39,11 +41,28 @@ def _compile(src: str, force: bool) -> str:
                      os.path.getmtime(os.path.join(ROOT, "include", "letkf.h")))
         if os.path.getmtime(obj) >= newest:
             return obj
-    cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + ["-Rpass-analysis=kernel-resource-usage", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
+    _check_scratch(src, r.stderr)
     return obj
+
+
+def _check_scratch(src: str, remarks: str) -> None:
+    """Every kernel is written to live in registers and LDS: a kernel that
+    spills more than MAX_SCRATCH bytes per lane is a build error (a large
+    private segment also makes the runtime's scratch allocation fail)."""
+    name = None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > MAX_SCRATCH:
+            raise RuntimeError(f"{src}: kernel {name} spills {m.group(1)} bytes per lane "
+                               f"(limit {MAX_SCRATCH})")
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
