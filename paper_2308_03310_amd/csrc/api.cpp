@@ -228,9 +228,14 @@ EvdArgs evd_desc(const ProblemWs& w, int* status) {
   ea.npts = w.npts;
   ea.alpha = (double)(p.k - 1) / p.infl;
   ea.sqrt_km1 = std::sqrt((double)(p.k - 1));
-  // Q carries the rounding of its contractions: FP64 unit roundoff for the
-  // FP64 form, FP32's for the FP32 and BF16 forms (FP32 accumulation).
-  ea.defl_eps = p.precision == LETKF_PREC_FP64 ? 0x1p-52 : 0x1p-24;
+  // Q carries the rounding of its contractions, and the divide and conquer
+  // deflates at a matching level: FP64 unit roundoff for the FP64 form,
+  // FP32's for the FP32 form; the BF16 form's operands are rounded to 8 bits,
+  // so its C is uncertain at about 2^-8 relative and 2^-16 stays far below
+  // that noise (measured: the BF16 error is unchanged against 2^-24).
+  ea.defl_eps = p.precision == LETKF_PREC_FP64   ? 0x1p-52
+                : p.precision == LETKF_PREC_FP32 ? 0x1p-24
+                                                 : 0x1p-16;
   ea.xt = w.xt;
   ea.abort_flag = w.abort_flag;
   ea.status = status;
