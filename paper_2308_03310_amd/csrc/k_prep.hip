@@ -71,20 +71,24 @@ __global__ void k_obs_scatter(ObsArgs a) {
 }
 
 // Order each cell's observations by their index so that every later sum runs
-// in an order fixed by the input alone (bitwise reproducible results).
-__global__ void k_cell_sort(ObsArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.ncells) return;
+// in an order fixed by the input alone (bitwise reproducible results): one
+// thread per slot counts the smaller indices in its cell (its rank) and
+// writes its observation there, into obs_cell (whose per-observation cells
+// are no longer needed: the cell is recomputed from the coordinates).
+__global__ void k_cell_rank(ObsArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.cell_start[a.ncells]) return;
+  const int j = a.perm[s];
+  const int c = (a.iy[j] / a.cb) * a.ncx + a.ix[j] / a.cb;
   const int lo = a.cell_start[c], hi = a.cell_start[c + 1];
-  for (int i = lo + 1; i < hi; ++i) {
-    const int v = a.perm[i];
-    int j = i - 1;
-    while (j >= lo && a.perm[j] > v) {
-      a.perm[j + 1] = a.perm[j];
-      --j;
-    }
-    a.perm[j + 1] = v;
-  }
+  int rank = 0;
+  for (int t = lo; t < hi; ++t) rank += a.perm[t] < j ? 1 : 0;
+  a.obs_cell[lo + rank] = j;
+}
+
+__global__ void k_cell_copy(ObsArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < a.cell_start[a.ncells]) a.perm[s] = a.obs_cell[s];
 }
 
 // xb[k][9][npts] -> xt[npts][9][k]: one 64-point x (all members) tile of one
@@ -189,7 +193,9 @@ hipError_t launch_bin(const ObsArgs& a, hipStream_t s) {
   if (a.n_obs > 0) {
     hipLaunchKernelGGL(k_obs_scatter, dim3(ceil_div(a.n_obs, 256)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cell_sort, dim3(ceil_div(a.ncells, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cell_rank, dim3(ceil_div(a.n_obs, 256)), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_copy, dim3(ceil_div(a.n_obs, 256)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -18,7 +18,8 @@ struct ObsArgs {
   const int32_t* kind;
   const double* val;
   const double* var;
-  int* obs_cell;    // [n_obs]   cell of each observation, -1 if invalid
+  int* obs_cell;    // [n_obs]   cell of each observation, -1 if invalid; after the
+                    //           scatter, scratch for the ordering of the cells
   int* cell_count;  // [ncells]
   int* cell_start;  // [ncells + 1] exclusive scan; cell_start[ncells] = valid count
   int* cell_fill;   // [ncells]
