@@ -30,6 +30,21 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// *p copied into scalar registers (the fields are read per lane, then taken
+// from the first lane): for a descriptor whose address is uniform but whose
+// memory the compiler cannot prove unwritten (a kernel that also does
+// atomics), so that it would otherwise keep every field in vector registers.
+template <typename T>
+__device__ __forceinline__ T uniform_copy(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "uniform_copy: size must be a multiple of 4");
+  T out;
+  const int* src = reinterpret_cast<const int*>(p);
+  int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return out;
+}
+
 // p[i] read as global memory.  Pointers that arrive inside a descriptor are
 // generic to the compiler, and a generic (flat) load counts against the LDS
 // wait counter too, so a wait for an LDS read would also wait for it; a

@@ -132,7 +132,7 @@ __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* 
   // cell table go through scalar registers and scalar loads
   const int gidx = __builtin_amdgcn_readfirstlane(bm.g0 + pl);
   const int prob = __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx));
-  const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
+  const GramArgs g = uniform_copy(bm.g + prob);   // copied once, into scalar registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];  // point within its problem
   const int x = pt % g.nx, y = pt / g.nx;

@@ -173,7 +173,7 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
   // the point is the wavefront's: uniform (scalar registers and loads)
   const int gidx = __builtin_amdgcn_readfirstlane(bm.g0 + pl);
   const int prob = __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx));
-  const GramArgs g = bm.g[prob];   // copied once: fields stay in registers
+  const GramArgs g = uniform_copy(bm.g + prob);   // copied once, into scalar registers
   if (*g.abort_flag) return;
   const int pt = gidx - bm.prefix[prob];
   const int x = pt % g.nx, y = pt / g.nx;

@@ -56,32 +56,44 @@ __device__ __forceinline__ int cell_intervals(int c, int R, int n, int cb, int n
   return 2;
 }
 
-// Position in the walk: cell row cy of y-interval yi, x-interval xi, whose
-// observations (sorted by cell) are [s, s1) from the current batch on.  All
-// fields are the same on every lane (the point is the wavefront's): they are
-// kept in scalar registers and the cell table is read with scalar loads.
+// Position in the walk.  The window's cell ranges (one per cell row and
+// x-interval: observations [s, s1) of cells xlo..xhi of row cy, sorted by
+// cell) are numbered r = 0, 1, ..; their bounds are read 64 at a time, range
+// base + l by lane l in one round of loads, and taken from the lanes as the
+// walk reaches them, so the walk waits on memory once per 64 ranges rather
+// than once per range.  Every field but vs, vs1 is the same on all lanes (the
+// point is the wavefront's).
 struct WindowCursor {
-  int nyi, nxi;
-  int ylo0, yhi0, ylo1, yhi1, xlo0, xhi0, xlo1, xhi1;
-  int yi, cy, xi;
-  int s, s1;
+  int nxi, n0, nranges;                   // x-intervals, rows of y-interval 0, ranges
+  int ylo0, ylo1, xlo0, xhi0, xlo1, xhi1;
+  int r, base;                            // current range; first range of the loaded chunk
+  int vs, vs1;                            // this lane's range of the chunk (range base + lane)
+  int s, s1;                              // current batch start and range end
 };
+
+// Bounds of ranges base .. base + 63, range base + l to lane l.
+__device__ __forceinline__ void window_load_chunk(WindowCursor& c, const GramArgs& g) {
+  const int r = c.base + lane_id();
+  c.vs = c.vs1 = 0;
+  if (r < c.nranges) {
+    const int rr = r / c.nxi, xi = r - rr * c.nxi;
+    const int cy = rr < c.n0 ? c.ylo0 + rr : c.ylo1 + (rr - c.n0);
+    const int row = cy * g.ncx;
+    c.vs = ldg(g.cell_start, row + (xi == 0 ? c.xlo0 : c.xlo1));
+    c.vs1 = ldg(g.cell_start, row + (xi == 0 ? c.xhi0 : c.xhi1) + 1);
+  }
+}
 
 // Moves to the next non-empty range; false when the window is exhausted.
 __device__ __forceinline__ bool window_next_range(WindowCursor& c, const GramArgs& g) {
   for (;;) {
-    if (++c.xi >= c.nxi) {
-      c.xi = 0;
-      if (++c.cy > (c.yi == 0 ? c.yhi0 : c.yhi1)) {
-        if (++c.yi >= c.nyi) return false;
-        c.cy = c.ylo1;
-      }
+    if (++c.r >= c.nranges) return false;
+    if (c.r - c.base >= 64) {
+      c.base += 64;
+      window_load_chunk(c, g);
     }
-    const int row = c.cy * g.ncx;
-    const int i0 = __builtin_amdgcn_readfirstlane(row + (c.xi == 0 ? c.xlo0 : c.xlo1));
-    const int i1 = __builtin_amdgcn_readfirstlane(row + (c.xi == 0 ? c.xhi0 : c.xhi1) + 1);
-    c.s = ldg(g.cell_start, i0);
-    c.s1 = ldg(g.cell_start, i1);
+    c.s = __builtin_amdgcn_readlane(c.vs, c.r - c.base);
+    c.s1 = __builtin_amdgcn_readlane(c.vs1, c.r - c.base);
     if (c.s < c.s1) return true;
   }
 }
@@ -95,14 +107,14 @@ __device__ __forceinline__ bool window_begin(WindowCursor& c, const GramArgs& g,
   c.xlo1 = lo[1];
   c.xhi1 = hi[1];
   lo[1] = hi[1] = 0;
-  c.nyi = cell_intervals(y, g.R, g.ny, g.cb, g.ncy, lo, hi);
+  const int nyi = cell_intervals(y, g.R, g.ny, g.cb, g.ncy, lo, hi);
   c.ylo0 = lo[0];
-  c.yhi0 = hi[0];
   c.ylo1 = lo[1];
-  c.yhi1 = hi[1];
-  c.yi = 0;
-  c.cy = c.ylo0;
-  c.xi = -1;
+  c.n0 = hi[0] - lo[0] + 1;
+  c.nranges = (c.n0 + (nyi > 1 ? hi[1] - lo[1] + 1 : 0)) * c.nxi;
+  c.r = -1;
+  c.base = 0;
+  window_load_chunk(c, g);
   return window_next_range(c, g);
 }
 
