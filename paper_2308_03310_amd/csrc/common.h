@@ -93,19 +93,50 @@ __device__ __forceinline__ double dpp_lane(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// The values of lanes l and l ^ W (W = 16 or 32) as a pair (a, b), in an
+// order that is the same on both lanes: v_permlane16_swap / v_permlane32_swap
+// (CDNA4) on two copies of x exchange the odd 16-lane rows (upper 32-lane
+// half) of one with the even rows (lower half) of the other, so one result
+// holds the lower row's value and the other the upper row's on every lane of
+// the pair.  A VALU exchange, with no LDS round trip.
+template <int W>
+__device__ __forceinline__ void row_pair(double x, double& a, double& b) {
+  static_assert(W == 16 || W == 32, "row_pair: W is 16 or 32");
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  if constexpr (W == 16) {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a = __hiloint2double(rh[0], rl[0]);
+    b = __hiloint2double(rh[1], rl[1]);
+  } else {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = __hiloint2double(rh[0], rl[0]);
+    b = __hiloint2double(rh[1], rl[1]);
+  }
+}
+
 // Sum over aligned groups of G lanes (G a power of two <= 64).  Stages within
-// 16 lanes use DPP; wider ones the swizzle network (32) and ds_bpermute (64).
-// Every stage pairs lanes symmetrically and IEEE addition is commutative, and
-// after each stage all lanes of a sub-group hold the same bits, so every lane
-// of a group receives the bitwise-identical total.
+// 16 lanes use DPP, the wider ones the row swaps above.  Every stage combines
+// the same two values on both lanes of a pair, and after each stage all
+// lanes of a sub-group hold the same bits, so every lane of a group receives
+// the bitwise-identical total.
 template <int G>
 __device__ __forceinline__ double group_sum(double x) {
   if constexpr (G >= 2) x += dpp_lane<0xB1>(x);
   if constexpr (G >= 4) x += dpp_lane<0x4E>(x);
   if constexpr (G >= 8) x += dpp_lane<0x141>(x);
   if constexpr (G >= 16) x += dpp_lane<0x140>(x);
-  if constexpr (G >= 32) x += xor_lane<16>(x);
-  if constexpr (G >= 64) x += xor_lane<32>(x);
+  if constexpr (G >= 32) {
+    double a, b;
+    row_pair<16>(x, a, b);
+    x = a + b;
+  }
+  if constexpr (G >= 64) {
+    double a, b;
+    row_pair<32>(x, a, b);
+    x = a + b;
+  }
   return x;
 }
 
@@ -116,8 +147,16 @@ __device__ __forceinline__ double group_max(double x) {
   if constexpr (G >= 4) x = fmax(x, dpp_lane<0x4E>(x));
   if constexpr (G >= 8) x = fmax(x, dpp_lane<0x141>(x));
   if constexpr (G >= 16) x = fmax(x, dpp_lane<0x140>(x));
-  if constexpr (G >= 32) x = fmax(x, xor_lane<16>(x));
-  if constexpr (G >= 64) x = fmax(x, xor_lane<32>(x));
+  if constexpr (G >= 32) {
+    double a, b;
+    row_pair<16>(x, a, b);
+    x = fmax(a, b);
+  }
+  if constexpr (G >= 64) {
+    double a, b;
+    row_pair<32>(x, a, b);
+    x = fmax(a, b);
+  }
   return x;
 }
 

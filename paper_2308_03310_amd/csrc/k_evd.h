@@ -58,10 +58,25 @@ struct EvdLds {
   };
 };
 
-// Value of x held by lane `src` of this lane's KP-lane group.
-template <int KP>
-__device__ __forceinline__ double group_read(double x, int src) {
-  return __shfl(x, src, KP);
+// Value of x held by lane SRC (compile-time) of this lane's KP-lane group.
+// With one or two groups per wavefront it comes from v_readlane (a VALU read
+// into scalar registers, no LDS round trip), the group's copy picked per
+// lane; with more, from a lane shuffle.
+template <int KP, int SRC>
+__device__ __forceinline__ double group_read_c(double x) {
+  static_assert(SRC >= 0 && SRC < KP, "group_read_c: source lane");
+  if constexpr (KP == 64) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), SRC),
+                            __builtin_amdgcn_readlane(__double2loint(x), SRC));
+  } else if constexpr (KP == 32) {
+    const double v0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), SRC),
+                                       __builtin_amdgcn_readlane(__double2loint(x), SRC));
+    const double v1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 32 + SRC),
+                                       __builtin_amdgcn_readlane(__double2loint(x), 32 + SRC));
+    return lane_id() < 32 ? v0 : v1;
+  } else {
+    return __shfl(x, SRC, KP);
+  }
 }
 
 // An integer the compiler cannot see through: LDS addresses derived from it
@@ -262,7 +277,7 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
     const double wj = fma(-2.0 * K, vj, p);
     a[i + 1] = fma(-wj, vv[i + 1], fma(-vj, pp[i + 1], a[i + 1]));
     if constexpr (more) {
-      alpha = group_read<KP>(a[i + 1], i + 2);
+      alpha = group_read_c<KP, i + 2>(a[i + 1]);
       sig = group_sum<KP>(jj > i + 2 ? a[i + 1] * a[i + 1] : 0.0);
     }
 #pragma unroll
@@ -281,7 +296,7 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
     const double v1 = vb[i + 1], p1 = pb[i + 1];
     a[i + 1] = fma(-wj, v1, fma(-vj, p1, a[i + 1]));
     if constexpr (more) {
-      alpha = group_read<KP>(a[i + 1], i + 2);
+      alpha = group_read_c<KP, i + 2>(a[i + 1]);
       sig = group_sum<KP>(jj > i + 2 ? a[i + 1] * a[i + 1] : 0.0);
     }
     constexpr int CH2 = 8;
@@ -302,7 +317,7 @@ template <int KP, int... Is>
 __device__ __forceinline__ void tridiag_steps(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
                                               double& ej,
                                               std::integer_sequence<int, Is...>) {
-  double alpha = group_read<KP>(a[0], 1);
+  double alpha = group_read_c<KP, 1>(a[0]);
   double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
   (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig, ej), ...);
 }
