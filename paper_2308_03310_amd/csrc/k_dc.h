@@ -80,6 +80,14 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(y, e, y);
 }
 
+// 1/x to about 10 ulps (the estimate carries about 24 bits; one
+// Newton-Raphson step): for the far terms of the secular sums, whose
+// rounding the convergence test already allows for (4 eps K sum |terms|).
+__device__ __forceinline__ double frcp1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+
 // The root of  c0 + B1/(p1 - t) + B2/(p2 - t) = 0  (p1 < p2, B1, B2 >= 0: the
 // function rises from -inf to +inf between the poles) that lies in the
 // bracket (lo, hi) inside (p1, p2); NaN if neither root of the quadratic
@@ -224,8 +232,8 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
 #pragma unroll 4
     for (; o + 1 < nfar; o += 2) {
       const double2 p = far[o], q = far[o + 1];
-      const double r0 = frcp((p.x - dorg) - tau);
-      const double r1 = frcp((q.x - dorg) - tau);
+      const double r0 = frcp1((p.x - dorg) - tau);
+      const double r1 = frcp1((q.x - dorg) - tau);
       const double t0 = p.y * r0, t1 = q.y * r1;
       const double u0 = t0 * r0, u1 = t1 * r1;
       F0 += t0;
@@ -239,7 +247,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
     }
     if (o < nfar) {
       const double2 p = far[o];
-      const double r0 = frcp((p.x - dorg) - tau);
+      const double r0 = frcp1((p.x - dorg) - tau);
       const double t0 = p.y * r0;
       const double u0 = t0 * r0;
       F0 += t0;
