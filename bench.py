@@ -160,23 +160,28 @@ def precision_form(L, torch, steps: int):
     return res
 
 
-def batching_form(L, torch, n: int, grids):
+def batching_form(L, torch, n: int, grids, precision: str):
     """The batching form: n independent problems drawn by the mixed-batch
     recipe (lattice sizes from grids, k from {16, 32, 64}, random masks with
-    clustered gaps), timed as one batched call with the default launch
-    settings, after letkf_tune, and as one call per problem."""
+    clustered gaps), in the given precision form, timed as one batched call
+    with the default launch settings, after letkf_tune, and as one call per
+    problem."""
     dev = torch.device("cuda:0")
+    prec = {"fp64": L.LETKF_PREC_FP64, "fp32": L.LETKF_PREC_FP32, "bf16": L.LETKF_PREC_BF16}[precision]
     wls = synth.batching_workloads(n, seed=3, grids=grids)
     probs, ios, keep = [], [], []
     n_obs = []
     for i, wl in enumerate(wls):
+        if i % 16 == 0:
+            print(f"batching form: generating problem {i} of {n}", file=sys.stderr, flush=True)
         p = synth.make_problem(wl)
         obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
                     (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
         xb = torch.from_numpy(p.xb).to(dev)
         xa = torch.empty_like(xb)
         keep.append((xb, xa, obs))
-        probs.append(L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl))
+        probs.append(L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl,
+                                    precision=prec))
         ios.append(L.make_io(i, xb, xa, obs))
         n_obs.append(len(p.obs_ix))
         del p
@@ -211,7 +216,7 @@ def batching_form(L, torch, n: int, grids):
         del keep
         torch.cuda.empty_cache()
     rate = lambda ms: round(points / (ms / 1e3), 1)
-    return {"problems": n, "grids": list(grids), "grid_points": points,
+    return {"problems": n, "grids": list(grids), "precision": precision, "grid_points": points,
             "obs_per_problem": [min(n_obs), max(n_obs)],
             "batched_default": {"ms": round(ms_default, 3), "value": rate(ms_default)},
             "batched_tuned": {"ms": round(ms_tuned, 3), "value": rate(ms_tuned), "setting": tune},
@@ -258,6 +263,8 @@ def main():
                     help="problems of the mixed-batch measurement (0 to skip)")
     ap.add_argument("--batching-grids", default="64,128,256",
                     help="lattice edges the mixed batch draws from")
+    ap.add_argument("--batching-precision", default="fp32", choices=("fp64", "fp32", "bf16"),
+                    help="precision form of the mixed batch (its recipe names the FP32 path)")
     ap.add_argument("--precision-steps", type=int, default=2,
                     help="timed analyses per precision form on the 1024^2, k = 64 workload "
                          "(0 to skip)")
@@ -375,7 +382,8 @@ def main():
         out["precision_form"] = precision_form(L, torch, args.precision_steps)
     if args.batching_problems > 0:
         out["batching_form"] = batching_form(L, torch, args.batching_problems,
-                                             tuple(int(g) for g in args.batching_grids.split(",")))
+                                             tuple(int(g) for g in args.batching_grids.split(",")),
+                                             args.batching_precision)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
