@@ -12,8 +12,8 @@
 // wavefront, 64/KP matrices per wavefront):
 //   1. Householder reduction to tridiagonal form T = H^T Q H (Golub & Van
 //      Loan, Matrix Computations, Sec. 8.3.1), one matrix row per lane in
-//      registers; the reflector of step i is broadcast through LDS and the
-//      symmetric rank-2 update A -= v w^T + w v^T runs in-lane;
+//      registers; the reflector of step i and p = tau A v are broadcast
+//      through LDS and the symmetric rank-2 update runs in-lane;
 //   2. eigenpairs of T by divide and conquer (k_dc.h): T = Q_T diag(lam) Q_T^T;
 //   3. back-transformation V = H Q_T = H_0 (H_1 (.. H_{n-3} Q_T)), one column
 //      of V per lane.
@@ -33,11 +33,11 @@ namespace letkf {
 
 // LDS per block: the matrix area (input staging, then the merge matrices of
 // the divide and conquer, then the Householder vectors with row stride KP,
-// then V in natural layout with row stride KP+1), the tridiagonal (d, e), the
-// reflector scalars tau, and a union of the tridiagonalization's broadcast
-// vectors, the divide-and-conquer work arrays and the transform's 5 x KP area
-// (Lambda^-1 V^T b, then dX and dX V for up to five of the nine components at
-// a time).
+// then V in natural layout with row stride KP+1) and a union of the
+// tridiagonalization's broadcast vectors, the divide-and-conquer work arrays
+// and the transform's 5 x KP area (Lambda^-1 V^T b, then dX and dX V for up
+// to five of the nine components at a time).  The tridiagonal (d, e) stays
+// in lane registers, and each reflector's tau is recovered from its vector.
 constexpr int kCompGroup = 5;
 
 #ifndef LETKF_REFL_REG_MAX
