@@ -84,12 +84,15 @@ __device__ __forceinline__ double xor_lane(double x) {
 
 // Value of x from the lane that a DPP pattern selects within each row of 16
 // lanes (CDNA data-parallel primitives: a VALU move, no LDS round trip).
+// Every pattern below writes every lane, so the move needs no prior value
+// in its destination (mov_dpp rather than update_dpp, which would cost an
+// extra move to initialize it).
 //   0xB1 quad_perm [1,0,3,2]  (lane ^ 1)       0x4E quad_perm [2,3,0,1]  (lane ^ 2)
 //   0x141 row_half_mirror     (i <-> 7 - i)    0x140 row_mirror         (i <-> 15 - i)
 template <int CTRL>
 __device__ __forceinline__ double dpp_lane(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
