@@ -109,16 +109,21 @@ __device__ __forceinline__ double two_pole_root(double c0, double B1, double B2,
 }
 
 
-// One model step of the secular iteration at the iterate t (origin-shifted):
-// the near terms W1/(P1 - x) + W2/(P2 - x) exact, the far sum (value F,
-// slope Fd, half curvature Fh at t) replaced by c + s1/(P1 - x) + s2/(P2 - x)
-// matched to it in value, slope and curvature (interior root) or in value
-// and slope on P1 alone (root above the last pole); returns the model's root
-// in (lo, hi), or NaN.
-__device__ __forceinline__ double secular_model_step(double irho, double F, double Fd, double Fh,
-                                                     double W1, double W2, double P1, double P2,
-                                                     double t, double lo, double hi, bool last,
-                                                     int K) {
+// One model step of the secular iteration at the iterate t (origin-shifted),
+// given f = f(t) and the near terms t1 = W1/(P1 - t), t2 = W2/(P2 - t): the
+// near terms exact, the far sum (slope Fd, half curvature Fh at t) replaced
+// by c + s1/(P1 - x) + s2/(P2 - x) matched to it in value, slope and
+// curvature (interior root) or in value and slope on P1 alone (root above
+// the last pole).  The model is solved for the step eta = x - t around the
+// evaluated f rather than for x from its constant and pole weights: a far
+// pole next to a near one puts a large weight on the other model pole, and
+// the constant then cancels against that pole's term, which would lose f
+// (and stall the iteration short of the root).  Returns the model's root in
+// (lo, hi), or NaN.
+__device__ __forceinline__ double secular_model_step(double f, double t1, double t2, double Fd,
+                                                     double Fh, double P1, double P2, double t,
+                                                     double lo, double hi, bool last, int K,
+                                                     double irho) {
   const double g1 = P1 - t, g2 = P2 - t;
   // split of F' over the model poles: a1 = s1/g1^2, a2 = s2/g2^2
   double a1, a2;
@@ -130,18 +135,21 @@ __device__ __forceinline__ double secular_model_step(double irho, double F, doub
     a1 = fmax((Fh * g2 - Fd) * g1 * ig, 0.0);
     a2 = fmax((Fd - Fh * g1) * g2 * ig, 0.0);
   }
-  const double c0 = irho + F - a1 * g1 - a2 * g2;
-  const double B1 = W1 + a1 * g1 * g1, B2 = W2 + a2 * g2 * g2;
-  if (!last) return two_pole_root(c0, B1, B2, P1, P2, lo, hi);
-  if (K == 1) return c0 > 0.0 ? P2 + B2 * frcp(c0) : __builtin_nan("");
-  // root above both model poles: the larger root of the quadratic
-  if (!(c0 > 0.0)) return __builtin_nan("");
-  const double aa = c0, bb = -(c0 * (P1 + P2) + B1 + B2);
-  const double cc = c0 * P1 * P2 + B1 * P2 + B2 * P1;
-  const double disc = fmax(bb * bb - 4.0 * aa * cc, 0.0);
-  const double q = -0.5 * (bb + (bb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
-  const double r1 = q * frcp(aa), r2 = q != 0.0 ? cc * frcp(q) : r1;
-  return fmax(r1, r2);
+  // a single pole (no far terms): f(x) = 1/rho + W2/(P2 - x) has its root at
+  // P2 + rho W2, with W2 = t2 g2
+  if (K == 1) return P2 + t2 * g2 * frcp(irho);
+  // the model's pole terms at t, and the model times (g1 - eta)(g2 - eta):
+  //   A eta^2 + B eta + C = 0
+  const double s1 = t1 + a1 * g1, s2 = t2 + a2 * g2;
+  const double A = f - s1 - s2;
+  const double B = s1 * g2 + s2 * g1 - f * (g1 + g2);
+  const double C = f * g1 * g2;
+  if (A == 0.0) return B != 0.0 ? t - C * frcp(B) : __builtin_nan("");
+  const double disc = fmax(B * B - 4.0 * A * C, 0.0);
+  const double q = -0.5 * (B + (B >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+  const double x1 = t + q * frcp(A);
+  const double x2 = q != 0.0 ? t + C * frcp(q) : __builtin_nan("");
+  return (x1 > lo && x1 < hi) ? x1 : x2;
 }
 
 // Root i (0-based) of f(lambda) = 1/rho + sum_j w_j^2/(d_j - lambda) = 0 over
@@ -156,7 +164,8 @@ __device__ __forceinline__ double secular_model_step(double irho, double F, doub
 // convergence, and s1, s2 >= 0 for an interior root, so the model rises
 // monotonically between its poles.  For the root above the last pole both
 // model poles lie below it and the far terms are matched in value and slope
-// on P1 alone.  A bracket from the signs of f safeguards every step.
+// on P1 alone.  Each model is solved for the step from the iterate (see
+// secular_model_step).  A bracket from the signs of f safeguards every step.
 __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, double rho,
                                             double& tau_out, bool& conv) {
   const double irho = 1.0 / rho;
@@ -272,7 +281,7 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
       conv = true;
       break;
     }
-    const double tn = secular_model_step(irho, F, Fd, Fh, W1, W2, P1, P2, tau, lo, hi, last, K);
+    const double tn = secular_model_step(f, t1, t2, Fd, Fh, P1, P2, tau, lo, hi, last, K, irho);
     const bool inside = tn > lo && tn < hi;
     const double tnew = inside ? tn : 0.5 * (lo + hi);
     // a model step (not a bisection) this small has converged: the model

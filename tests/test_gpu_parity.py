@@ -165,6 +165,32 @@ def test_eigh_batched_hard_families(k, family):
         assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
 
 
+@pytest.mark.parametrize("k", [51, 52, 60])
+def test_eigh_batched_secular_near_pole_pairs(k):
+    # Wilkinson batches at these orders give merges where a root lies within
+    # ~1e-11 of a pole that has a second pole ~1e-11 on its other side: the
+    # secular iteration must still converge (status clean) and stay accurate.
+    import torch
+    n = 24
+    for rep in range(3):
+        say(f"eigh_batched wilkinson k={k} seed {rep}")
+        A = _hard_matrices(k, "wilkinson", n, np.random.default_rng(100000 * rep + 1000 * k + 2))
+        lam = torch.empty(n, k, dtype=torch.float64, device="cuda")
+        vec = torch.empty(n, k, k, dtype=torch.float64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        L.letkf_eigh_batched(torch.from_numpy(A).cuda(), lam, vec, st)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == 0
+        lam, vec = lam.cpu().numpy(), vec.cpu().numpy()
+        for i in range(n):
+            nrm = np.linalg.norm(A[i])
+            np.testing.assert_allclose(np.sort(lam[i]), np.linalg.eigvalsh(A[i]), rtol=0,
+                                       atol=1e-13 * nrm)
+            V = vec[i]
+            assert np.linalg.norm(V @ np.diag(lam[i]) @ V.T - A[i]) <= 1e-13 * nrm * k
+            assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
+
+
 # ------------------------------------------------------------ whole analyses
 def _oracle_full(p, L_len=None, infl=None, loc=orc.LOC_GAUSS, var=None):
     wl = p.wl
