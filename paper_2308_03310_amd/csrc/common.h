@@ -171,6 +171,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return xcd < rem ? xcd * (nb8 + 1) + idx : rem * (nb8 + 1) + (xcd - rem) * nb8 + idx;
 }
 
+// Block index remap for a launch over several problems whose cost per point
+// differs (observation density, localization length): runs of RUN
+// consecutive logical blocks go to one XCD and successive runs to successive
+// XCDs, so that every XCD gets a share of each problem (with xcd_remap a
+// contiguous eighth of the launch, possibly a whole heavy problem, sits on
+// one XCD and the launch waits for it), while the blocks of a run still
+// share their XCD's L2.  Blocks past the last whole round of 8 runs keep
+// their index.
+template <int RUN>
+__device__ __forceinline__ int xcd_remap_runs(int b, int nblocks) {
+  const int full = nblocks / (8 * RUN) * (8 * RUN);
+  if (b >= full) return b;
+  const int xcd = b & 7, idx = b >> 3;
+  return ((idx / RUN) * 8 + xcd) * RUN + idx % RUN;
+}
+
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // bfloat16 <-> float, round to nearest even (finite values).

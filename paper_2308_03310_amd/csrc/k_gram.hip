@@ -203,7 +203,9 @@ __global__ __launch_bounds__(256) void k_gram_f64(BatchMap bm) {
   __shared__ double w_ring[4][kRing];
   const int wid = threadIdx.x >> 6;
   if constexpr (!PERSIST) {
-    const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
+    const int blk = bm.nprob > 1 ? xcd_remap_runs<kBatchRun>(blockIdx.x, gridDim.x)
+                                 : xcd_remap(blockIdx.x, gridDim.x);
+    const int pl = blk * 4 + wid;
     if (pl < bm.n) gram_f64_point<KQ>(bm, pl, s_ring[wid], w_ring[wid]);
   } else {
     for_each_queued_point(bm, [&](int pl) { gram_f64_point<KQ>(bm, pl, s_ring[wid], w_ring[wid]); });

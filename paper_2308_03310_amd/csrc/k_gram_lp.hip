@@ -234,7 +234,9 @@ __global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
   __shared__ double w_ring[4][kRing];
   const int wid = threadIdx.x >> 6;
   if constexpr (!PERSIST) {
-    const int pl = xcd_remap(blockIdx.x, gridDim.x) * 4 + wid;
+    const int blk = bm.nprob > 1 ? xcd_remap_runs<kBatchRun>(blockIdx.x, gridDim.x)
+                                 : xcd_remap(blockIdx.x, gridDim.x);
+    const int pl = blk * 4 + wid;
     if (pl < bm.n) gram_lp_point<KQ, PREC>(bm, pl, s_ring[wid], w_ring[wid]);
   } else {
     for_each_queued_point(bm, [&](int pl) { gram_lp_point<KQ, PREC>(bm, pl, s_ring[wid], w_ring[wid]); });

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef LETKF_BATCH_RUN
+#define LETKF_BATCH_RUN 32
+#endif
+
 namespace letkf {
 
 // Observation binning (uniform cells of cb x cb lattice points) and the
@@ -99,6 +103,8 @@ struct BatchMap {
 // dispatched round-robin over the 8 XCDs), each over a contiguous eighth of
 // the slab; a wavefront that drains its own moves on to the next XCD's.
 constexpr int kQueueSlots = 8;
+// Blocks (of 4 points) per XCD run when a Gram launch covers several problems.
+constexpr int kBatchRun = LETKF_BATCH_RUN;
 constexpr int kPersistentBlocksPerCu = 8;
 constexpr int kDeviceCus = 256;
 
