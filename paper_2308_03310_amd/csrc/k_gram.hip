@@ -192,7 +192,9 @@ __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* 
 }
 
 // Grid form: one wavefront per point, four points per block, blocks remapped
-// so that neighbouring points (which share observations) stay on one XCD.
+// so that neighbouring points (which share observations) stay on one XCD:
+// contiguous eighths of a one-problem launch, interleaved runs of blocks
+// when the launch covers several problems (whose cost per point differs).
 // Persistent form: a device-filling grid whose wavefronts take points from
 // per-XCD work queues over contiguous eighths of the slab and, once their
 // own eighth is done, from the others' (load balance when the local
