@@ -1,12 +1,20 @@
 #!/usr/bin/env python3
-"""Throughput of the LETKF local analysis on one MI355X.
+"""Throughput of the LETKF local analysis on one MI355X: mixed precision
+against plain FP64.
 
 One step = one whole analysis (observation binning, transpose, forecast
 observations, localized Gram, eigensolve + transform + update, transpose
-back) of a synthetic D2Q9 ensemble already resident in HBM.  Prints one JSON
-line: grid-point analyses/s, per-phase GPU times from HIP events recorded on
-the analysis stream, the roofline position of the dominant kernel and the
-CPU oracle's rate on a bounded sample of the same workload.
+back) of the 1024 x 1024, k = 64 synthetic D2Q9 ensemble, already resident in
+HBM.  The headline `value` is the mixed-precision form (Gram and update
+contractions in FP32 on MFMA with FP32 accumulation, FP64 eigensolve and
+eigenvalue scaling); the same K steps are timed in the plain FP64 form and
+the BF16 form, and their ratio is reported.  Prints one JSON line with
+per-phase GPU times from HIP events recorded on the analysis stream, the
+roofline position of the dominant kernel, each form's error against the FP64
+oracle at sampled grid points (whole, mean, spread), the oracle's own rate on
+the host's cores, and the secondary measurements: the 256 x 256, k = 32 FP64
+workload, the batched eigensolve at the shapes of the paper's Table I, the
+serving run and the batching form.
 """
 from __future__ import annotations
 
@@ -29,6 +37,12 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
 # dense MFMA peaks of the Gram contraction by precision form
 PEAK_GRAM_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+FORMS = (("fp64", 0), ("fp32", 1), ("bf16", 2))
+KERNEL_NAMES = {"gram": {"fp64": "k_gram_f64", "fp32": "k_gram_lp", "bf16": "k_gram_lp"},
+                "evd_update": "k_evd"}
+# Batched EVD of 16,384 matrices from the LBM-LETKF model on one A100 (FP32,
+# the paper's Table I, EigenG column): context for the eigensolve record.
+PAPER_TABLE1_EIGENG_MS = {16: 1.3, 32: 2.4, 48: 7.8, 64: 14.2}
 
 
 def local_counts_regular(wl) -> np.ndarray:
@@ -50,18 +64,20 @@ def local_counts_regular(wl) -> np.ndarray:
 
 
 def algorithmic_flops(wl):
-    """Per-analysis algorithmic flop counts of the two dominant kernels.
+    """Per-analysis algorithmic flop counts of the two dominant kernels, per
+    grid point:
 
-    gram: SYRK of the local perturbations, p k (k+1), plus the right-hand side 2 p k,
-          with p = scalar local observations of the point;
-    evd:  symmetric eigendecomposition 9 k^3 (Golub & Van Loan's count for the
-          symmetric QR algorithm with eigenvectors), plus V^T b and V z (4 k^2),
-          dX V and (dX V D) V^T for the nine components (36 k^2).
+    gram:       SYRK of the local perturbations p k (k+1) plus the right-hand
+                side 2 p k, p = scalar local observations of the point;
+    evd_update: symmetric eigendecomposition with vectors 9 k^3 (Golub & Van
+                Loan's count), the transform V diag V^T of the symmetric square
+                root 2 k^3 + 4 k^2, and the update of the nine components
+                2 * 9 k^2.
     """
     k = wl.k
     p = local_counts_regular(wl).astype(np.float64) * len(wl.kinds)
     gram = float(np.sum(p * (k * (k + 1) + 2 * k)))
-    evd = float(wl.nx * wl.ny * (9 * k ** 3 + 40 * k ** 2))
+    evd = float(wl.nx * wl.ny * (11 * k ** 3 + 22 * k ** 2))
     return {"gram": gram, "evd_update": evd}
 
 
@@ -85,17 +101,17 @@ def stored_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def timed_analyses(L, torch, wl, p, precision, steps, warmup, xb=None):
-    """Whole analyses of one problem at one precision form: returns (analyses/s,
-    ms per analysis, per-phase ms per analysis, launches per phase, the
-    analysis ensemble on the device)."""
-    dev = torch.device("cuda:0")
-    if xb is None:
-        xb = torch.from_numpy(p.xb).to(dev)
+def dev_obs(torch, p, dev):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                 (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
+
+
+def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup):
+    """steps whole analyses of one problem in one precision form on torch's
+    current stream, bracketed by synchronizations: returns (analyses/s, ms per
+    analysis, per-phase ms per analysis, launches per phase, the analysis)."""
     xa = torch.empty_like(xb)
-    obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
-                (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
-    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl,
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, int(obs[0].numel()), wl.L, wl.infl,
                                         precision=precision)], flags=L.LETKF_FLAG_PHASE_TIMING)
     try:
         io = [L.make_io(0, xb, xa, obs)]
@@ -103,9 +119,13 @@ def timed_analyses(L, torch, wl, p, precision, steps, warmup, xb=None):
         for _ in range(warmup):
             L.letkf_analyze(plan, io, stream)
         torch.cuda.synchronize()
-        L.letkf_phase_times(plan)
+        L.letkf_phase_times(plan)                      # drop the warm-up calls
+        st = L.letkf_status(plan, sync=True)
+        if st != L.LETKF_OK:
+            raise SystemExit(f"{wl.name} precision {precision} warm-up: {L.letkf_strerror(st)}")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(steps):
             L.letkf_analyze(plan, io, stream)
@@ -122,74 +142,117 @@ def timed_analyses(L, torch, wl, p, precision, steps, warmup, xb=None):
     return wl.nx * wl.ny / (ms / 1e3), ms, per_call, launches, xa
 
 
-def precision_form(L, torch, steps: int):
-    """The precision form on the 1024 x 1024, k = 64 workload: FP64 baseline,
-    FP32 and BF16 Gram/update contractions (FP64 eigensolve and eigenvalue
-    scaling in all three).  Errors are taken against the FP64 path over the
-    whole field (the FP64 path itself is held to the oracle by the tests)."""
-    wl = synth.WORKLOADS["grid1024_k64"]
-    p = synth.make_problem(wl)
-    xb = torch.from_numpy(p.xb).to(torch.device("cuda:0"))
-    gram_flops = algorithmic_flops(wl)["gram"]
-    res = {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "k": wl.k, "steps": steps,
-           "errors": "relative L2 over every entry of the analysis ensemble, against the "
-                     "FP64 path"}
-    base = ref = None
-    for name, prec in (("fp64", L.LETKF_PREC_FP64), ("fp32", L.LETKF_PREC_FP32),
-                       ("bf16", L.LETKF_PREC_BF16)):
-        rate, ms, ph, launches, xa = timed_analyses(L, torch, wl, p, prec, steps, 1, xb)
-        gram_tf = gram_flops / (ph["gram"] / 1e3) / 1e12
-        r = {"value": round(rate, 1), "unit": "grid-point analyses/s", "ms_per_analysis": round(ms, 3),
-             "gram_ms": round(ph["gram"], 4), "evd_update_ms": round(ph["evd_update"], 3),
-             "gram_tflops": round(gram_tf, 3),
-             "gram_frac_of_mfma_peak": round(gram_tf / PEAK_GRAM_TFLOPS[name], 4),
-             "gram_peak_tflops": PEAK_GRAM_TFLOPS[name]}
-        if base is None:
-            base, ref = r, xa
-        else:
-            r["rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(xa - ref) /
-                                        torch.linalg.vector_norm(ref))
-            r["increment_rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(xa - ref) /
-                                                  torch.linalg.vector_norm(ref - xb))
-            r["speedup_vs_fp64"] = round(rate / base["value"], 3)
-            r["gram_speedup_vs_fp64"] = round(base["gram_ms"] / r["gram_ms"], 3)
-            del xa
-        res[name] = r
-    del ref, xb
+def kernel_roofline(wl, form, per_call, launches):
+    """Achieved rate of the Gram and eigensolve/update kernels: algorithmic
+    flops per launch over the average launch time from the HIP events."""
+    flops = algorithmic_flops(wl)
+    out = {}
+    for ph, bound, peak in (("gram", "mfma", PEAK_GRAM_TFLOPS[form]),
+                            ("evd_update", "alu", PEAK_FP64_TFLOPS)):
+        n_l = max(launches[ph], 1)
+        ms_launch = per_call[ph] / n_l
+        ach = flops[ph] / n_l / (ms_launch / 1e3) / 1e12
+        name = KERNEL_NAMES[ph][form] if isinstance(KERNEL_NAMES[ph], dict) else KERNEL_NAMES[ph]
+        out[ph] = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
+                   "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                   "ms_per_launch": round(ms_launch, 4), "launches_per_step": n_l,
+                   "flops_per_launch": flops[ph] / n_l}
+    return out
+
+
+def oracle_errors(wl, p, xa, n_points, seed):
+    """Errors of an analysis against the FP64 oracle at seeded sample points:
+    relative L2 of the whole, of the increment, of the analysis mean and of
+    the spread, and the largest error of one point relative to its norm."""
+    from oracle import letkf_oracle as orc
+    pts = synth.sample_points(wl.nx, wl.ny, n_points, seed=seed)
+    ref = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
+                       wl.infl).run(pts)
+    iy, ix = pts // wl.nx, pts % wl.nx
+    got = np.moveaxis(xa[:, :, iy, ix].cpu().numpy(), -1, 0)        # [n, k, 9]
+    xb = np.moveaxis(p.xb[:, :, iy, ix], -1, 0)
+    d = got - ref
+    gm, rm = got.mean(axis=1, keepdims=True), ref.mean(axis=1, keepdims=True)
+    pt = np.linalg.norm(d.reshape(len(pts), -1), axis=1) / np.linalg.norm(
+        ref.reshape(len(pts), -1), axis=1)
+    return {"points": int(len(pts)),
+            "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "increment_rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref - xb)),
+            "mean_rel_l2": float(np.linalg.norm(gm - rm) / np.linalg.norm(rm)),
+            "spread_rel_l2": float(np.linalg.norm((got - gm) - (ref - rm)) /
+                                   np.linalg.norm(ref - rm)),
+            "max_point_rel": float(pt.max())}
+
+
+def eigh_table1(L, torch, batch=16384, ks=(16, 32, 48, 64), reps=10):
+    """The standalone batched eigensolve at the shapes of the paper's Table I
+    (16,384 matrices per batch): LETKF-form matrices ((k-1)/rho) I + Y^T Y
+    with Y of 2k centred rows."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(7)
+    out = {"batch": batch, "unit": "ns per matrix", "precision": "fp64",
+           "context": "paper Table I (EigenG, FP32, one A100), ms per 16,384 matrices"}
+    for k in ks:
+        Y = torch.randn(batch, 2 * k, k, generator=g, device=dev, dtype=torch.float64)
+        Y = Y - Y.mean(dim=2, keepdim=True)
+        A = torch.matmul(Y.transpose(1, 2).contiguous(), Y) * (1.0 / (2 * k)) + \
+            (k - 1) / 1.1 * torch.eye(k, device=dev, dtype=torch.float64)
+        A = A.contiguous()
+        lam = torch.empty(batch, k, dtype=torch.float64, device=dev)
+        vec = torch.empty(batch, k, k, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            L.letkf_eigh_batched(A, lam, vec, st)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            L.letkf_eigh_batched(A, lam, vec, st)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if int(st.item()) != 0:
+            raise SystemExit(f"eigh_batched k={k}: not converged")
+        # residual check on a few matrices
+        i = torch.arange(0, batch, batch // 8, device=dev)
+        R = torch.matmul(vec[i] * lam[i][:, None, :], vec[i].transpose(1, 2).contiguous()) - A[i]
+        res = float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(A[i])).max())
+        tf = 9 * k ** 3 * batch / (ms / 1e3) / 1e12
+        out[f"k{k}"] = {"ms": round(ms, 4), "ns_per_matrix": round(ms * 1e6 / batch, 1),
+                        "tflops_9k3": round(tf, 3), "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 4),
+                        "max_rel_residual": res, "paper_a100_fp32_ms": PAPER_TABLE1_EIGENG_MS.get(k)}
+        del Y, A, lam, vec
     torch.cuda.empty_cache()
-    return res
+    return out
 
 
-def batching_form(L, torch, n: int, grids, precision: str):
+def batching_form(L, torch, n: int, grids, precision: str, reps: int, tune: bool):
     """The batching form: n independent problems drawn by the mixed-batch
     recipe (lattice sizes from grids, k from {16, 32, 64}, random masks with
     clustered gaps), in the given precision form, timed as one batched call
-    with the default launch settings, after letkf_tune, and as one call per
-    problem."""
+    and as one call per problem (and after letkf_tune when asked).  The
+    ensembles are generated on the device by the recipe's generator."""
     dev = torch.device("cuda:0")
-    prec = {"fp64": L.LETKF_PREC_FP64, "fp32": L.LETKF_PREC_FP32, "bf16": L.LETKF_PREC_BF16}[precision]
+    prec = dict(FORMS)[precision]
     wls = synth.batching_workloads(n, seed=3, grids=grids)
-    probs, ios, keep = [], [], []
-    n_obs = []
+    probs, ios, keep, n_obs = [], [], [], []
     for i, wl in enumerate(wls):
-        if i % 16 == 0:
+        if i % 32 == 0:
             print(f"batching form: generating problem {i} of {n}", file=sys.stderr, flush=True)
-        p = synth.make_problem(wl)
-        obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
-                    (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
-        xb = torch.from_numpy(p.xb).to(dev)
+        xb, p = synth.make_problem_device(wl, dev)
+        obs = dev_obs(torch, p, dev)
         xa = torch.empty_like(xb)
         keep.append((xb, xa, obs))
         probs.append(L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl,
                                     precision=prec))
         ios.append(L.make_io(i, xb, xa, obs))
         n_obs.append(len(p.obs_ix))
-        del p
     points = sum(w.nx * w.ny for w in wls)
     plan = L.letkf_plan(probs)
     stream = torch.cuda.current_stream()
 
-    def timed(calls, reps=3):
+    def timed(calls):
         for c in calls:                                   # warm-up
             L.letkf_analyze(plan, c, stream)
         torch.cuda.synchronize()
@@ -204,10 +267,13 @@ def batching_form(L, torch, n: int, grids, precision: str):
         return e0.elapsed_time(e1) / reps
 
     try:
-        ms_default = timed([ios])
+        ms_batched = timed([ios])
         ms_single = timed([[io] for io in ios])
-        tune = L.letkf_tune(plan, ios, stream)
-        ms_tuned = timed([ios])
+        out = {"problems": n, "grids": list(grids), "precision": precision, "grid_points": points,
+               "obs_per_problem": [min(n_obs), max(n_obs)], "reps": reps}
+        if tune:
+            setting = L.letkf_tune(plan, ios, stream)
+            out["batched_tuned"] = {"ms": round(timed([ios]), 3), "setting": setting}
         st = L.letkf_status(plan, sync=True)
         if st != L.LETKF_OK:
             raise SystemExit(f"batching form: {L.letkf_strerror(st)}")
@@ -216,80 +282,102 @@ def batching_form(L, torch, n: int, grids, precision: str):
         del keep
         torch.cuda.empty_cache()
     rate = lambda ms: round(points / (ms / 1e3), 1)
-    return {"problems": n, "grids": list(grids), "precision": precision, "grid_points": points,
-            "obs_per_problem": [min(n_obs), max(n_obs)],
-            "batched_default": {"ms": round(ms_default, 3), "value": rate(ms_default)},
-            "batched_tuned": {"ms": round(ms_tuned, 3), "value": rate(ms_tuned), "setting": tune},
-            "one_call_per_problem": {"ms": round(ms_single, 3), "value": rate(ms_single)},
-            "unit": "grid-point analyses/s"}
+    out["batched"] = {"ms": round(ms_batched, 3), "value": rate(ms_batched)}
+    out["one_call_per_problem"] = {"ms": round(ms_single, 3), "value": rate(ms_single)}
+    out["batched_speedup"] = round(ms_single / ms_batched, 3)
+    out["unit"] = "grid-point analyses/s"
+    return out
 
 
-def cpu_baseline(wl, p, seconds: float):
-    """The oracle, as it is, on a bounded sample of the workload's grid points."""
+def _oracle_worker(args):
+    an, pts, nx, seconds = args
     from threadpoolctl import threadpool_limits
-    from oracle import letkf_oracle as orc
-    pts = synth.sample_points(wl.nx, wl.ny, wl.nx * wl.ny, seed=3)
     done = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        an = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
-                          wl.infl)
         for q in pts:
-            an.point(int(q) % wl.nx, int(q) // wl.nx)
+            an.point(int(q) % nx, int(q) // nx)
             done += 1
             if time.perf_counter() - t0 >= seconds:
                 break
         dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "grid-point analyses/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} seeded random grid points of {wl.name} (forecast observations of "
-                      f"all {len(p.obs_ix)} observations included), {dt:.1f} s, 1 BLAS thread"}
+    return done, dt
+
+
+def cpu_baseline(wl, p, seconds: float, max_cores: int):
+    """The oracle, as it is, on a bounded sample of the workload's grid points:
+    one process with one BLAS thread, then one such process per host core
+    (forked after the forecast observations are computed, so every process
+    evaluates points of the same analysis)."""
+    import multiprocessing as mp
+    from oracle import letkf_oracle as orc
+    pts = synth.sample_points(wl.nx, wl.ny, wl.nx * wl.ny, seed=3)
+    an = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L, wl.infl)
+    done1, dt1 = _oracle_worker((an, pts, wl.nx, seconds))
+    cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
+    chunks = [pts[i::cores] for i in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(an, c, wl.nx, seconds) for c in chunks])
+    done_n = sum(r[0] for r in res)
+    rate_n = sum(r[0] / r[1] for r in res)
+    return {"value": rate_n, "unit": "grid-point analyses/s", "cores": cores, "kind": "oracle",
+            "single_core_value": done1 / dt1,
+            "sample": f"seeded random grid points of {wl.name} (forecast observations of all "
+                      f"{len(p.obs_ix)} observations computed first): {done1} points in "
+                      f"{dt1:.1f} s on 1 core; {done_n} points in about {seconds:.0f} s on "
+                      f"{cores} processes of 1 BLAS thread each"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid256_k32", choices=sorted(synth.WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid1024_k64", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16"),
+                    help="the mixed form of the headline value")
+    ap.add_argument("--forms", default="fp64,fp32,bf16",
+                    help="precision forms timed (the headline's and fp64 are always included)")
+    ap.add_argument("--error-points", type=int, default=24,
+                    help="sample points at which each form is compared with the oracle (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-cores", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--secondary-steps", type=int, default=10,
+                    help="timed steps of the 256^2, k = 32 FP64 workload (0 to skip)")
+    ap.add_argument("--eigh-reps", type=int, default=10,
+                    help="timed batches of the Table I eigensolve shapes (0 to skip)")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving run (0 to skip)")
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "timed loop (the known-size reference for HBM byte counters)")
-    ap.add_argument("--batching-problems", type=int, default=64,
+    ap.add_argument("--batching-problems", type=int, default=256,
                     help="problems of the mixed-batch measurement (0 to skip)")
-    ap.add_argument("--batching-grids", default="64,128,256",
+    ap.add_argument("--batching-grids", default="64,128,256,512",
                     help="lattice edges the mixed batch draws from")
     ap.add_argument("--batching-precision", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision form of the mixed batch (its recipe names the FP32 path)")
-    ap.add_argument("--precision-steps", type=int, default=2,
-                    help="timed analyses per precision form on the 1024^2, k = 64 workload "
-                         "(0 to skip)")
+    ap.add_argument("--batching-reps", type=int, default=2)
+    ap.add_argument("--batching-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the analysis is measured on one MI355X; see DESIGN.md for how it shards)",
+              "(the analysis is measured on one MI355X; DESIGN.md describes how it shards)",
               file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2308_03310_amd import letkf as L
 
-    wl = synth.WORKLOADS[args.workload]
-    p = synth.make_problem(wl)
-    npts = wl.nx * wl.ny
     dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[args.workload]
+    print(f"generating {wl.name}", file=sys.stderr, flush=True)
+    p = synth.make_problem(wl)
     xb = torch.from_numpy(p.xb).to(dev)
-    xa = torch.empty_like(xb)
-    obs = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
-                (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
-    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl)],
-                        flags=L.LETKF_FLAG_PHASE_TIMING)
-    io = [L.make_io(0, xb, xa, obs)]
-    stream = torch.cuda.current_stream()
+    obs = dev_obs(torch, p, dev)
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib << 17            # doubles
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -298,94 +386,105 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        L.letkf_analyze(plan, io, stream)
-    torch.cuda.synchronize()
-    L.letkf_phase_times(plan)                     # drop the warm-up calls
-    st = L.letkf_status(plan, sync=True)
-    if st != L.LETKF_OK:
-        raise SystemExit(f"warm-up analysis failed: {L.letkf_strerror(st)}")
 
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        L.letkf_analyze(plan, io, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    calls, phase_ms, launches = L.letkf_phase_times(plan)
-    st = L.letkf_status(plan, sync=True)
-    L.letkf_plan_destroy(plan)
-    if st != L.LETKF_OK:
-        raise SystemExit(f"timed analysis failed: {L.letkf_strerror(st)}")
-    ms_step = ms_total / args.steps
-    value = npts * args.steps / (ms_total / 1e3)
+    forms = [f for f, _ in FORMS if f in set(args.forms.split(",")) | {"fp64", args.precision}]
+    res = {}
+    wall0 = time.perf_counter()
+    for name in forms:
+        print(f"timing the {name} form", file=sys.stderr, flush=True)
+        rate, ms, ph, launches, xa = timed_analyses(L, torch, wl, xb, obs, dict(FORMS)[name],
+                                                    args.steps, args.warmup)
+        r = {"value": round(rate, 1), "ms_per_analysis": round(ms, 3),
+             "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+             "kernels": kernel_roofline(wl, name, ph, launches)}
+        if args.error_points > 0:
+            r["errors_vs_oracle"] = oracle_errors(wl, p, xa, args.error_points, seed=11)
+        del xa
+        res[name] = r
+    wall = time.perf_counter() - wall0
+    head = res[args.precision]
+    base = res["fp64"]
+    for name in forms:
+        if name != "fp64":
+            res[name]["speedup_vs_fp64"] = round(res[name]["value"] / base["value"], 3)
+            res[name]["gram_speedup_vs_fp64"] = round(
+                base["phases_ms"]["gram"] / res[name]["phases_ms"]["gram"], 3)
 
-    flops = algorithmic_flops(wl)
-    per_call = {k: v / max(calls, 1) for k, v in phase_ms.items()}
-    kernels = {}
-    for ph, bound in (("gram", "mfma"), ("evd_update", "alu")):
-        n_l = max(launches[ph], 1)
-        ms_launch = per_call[ph] / n_l
-        ach = flops[ph] / n_l / (ms_launch / 1e3) / 1e12
-        kernels[ph] = {"bound": bound, "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
-                       "ms_per_launch": round(ms_launch, 4), "launches_per_step": n_l,
-                       "flops_per_launch": flops[ph] / n_l}
-    dom = max(kernels, key=lambda ph: per_call[ph])
-    kname = {"gram": "k_gram_f64", "evd_update": "k_evd"}[dom]
-    roof = {k: kernels[dom][k] for k in ("bound", "achieved", "peak", "unit", "frac")}
-    roof["kernel"] = kname
-    roof["traffic"] = stored_traffic(kname, wl.name)
+    dom = max(("gram", "evd_update"), key=lambda ph: head["phases_ms"][ph])
+    kd = head["kernels"][dom]
+    roof = {k: kd[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof["kernel"] = kd["kernel"]
+    roof["traffic"] = stored_traffic(kd["kernel"], f"{wl.name}_{args.precision}")
 
     out = {
-        "metric": "LETKF grid-point analyses/s",
-        "value": round(value, 1),
+        "metric": "LETKF grid-point analyses/s, mixed vs FP64 plain",
+        "value": head["value"],
         "unit": "grid-point analyses/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": head["ms_per_analysis"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": f"{args.precision}+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "k": wl.k,
                    "obs_stride": wl.stride, "obs_kinds": "u,v", "n_obs": int(len(p.obs_ix)),
-                   "L": wl.L, "infl": wl.infl, "sigma": wl.sigma, "precision": "fp64",
+                   "L": wl.L, "infl": wl.infl, "sigma": wl.sigma,
+                   "precision": f"{args.precision} Gram/update contractions (FP32 accumulation), "
+                                f"fp64 eigensolve and eigenvalue scaling",
                    "localization": "gauss(2L cutoff)"},
+        "speedup_vs_fp64": head["speedup_vs_fp64"],
+        "fp64_value": base["value"],
         "roofline": roof,
-        "kernels": kernels,
-        "phases_ms_per_step": {k: round(v, 4) for k, v in per_call.items()},
+        "forms": res,
         "host_wall_s": round(wall, 3),
     }
+    del xb, obs
+    torch.cuda.empty_cache()
+    if args.secondary_steps > 0:
+        w2 = synth.WORKLOADS["grid256_k32"]
+        p2 = synth.make_problem(w2)
+        xb2 = torch.from_numpy(p2.xb).to(dev)
+        rate, ms, ph, launches, xa2 = timed_analyses(L, torch, w2, xb2, dev_obs(torch, p2, dev), 0,
+                                                     args.secondary_steps, 2)
+        out["grid256_k32_fp64"] = {"value": round(rate, 1), "ms_per_analysis": round(ms, 4),
+                                   "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+                                   "kernels": kernel_roofline(w2, "fp64", ph, launches)}
+        del xb2, xa2
+        torch.cuda.empty_cache()
+    if args.eigh_reps > 0:
+        out["eigh_table1"] = eigh_table1(L, torch, reps=args.eigh_reps)
     if args.serving_requests > 0:
         from paper_2308_03310_amd import serving
-        srv = serving.AssimilationServer(serving.default_specs(16), budget_bytes=200 << 30,
-                                         n_slots=8)
+        print("serving", file=sys.stderr, flush=True)
+        specs = serving.default_specs(12)
+        srv = serving.AssimilationServer(specs, budget_bytes=200 << 30, n_slots=8)
         try:
-            srv.run_poisson(args.serving_rate, 16, seed=40)       # warm-up: admit every session
+            for i in range(len(specs)):                   # warm-up: admit every session once
+                srv.submit(serving.Request(i, i, time.perf_counter()))
+            srv.drain()
             out["serving"] = srv.run_poisson(args.serving_rate, args.serving_requests, seed=4)
-            out["serving"]["sessions"] = len(srv.sessions)
+            out["serving"]["sessions"] = [s.spec.name for s in srv.sessions]
             out["serving"]["cycle"] = "50 BGK steps (tau 0.52, Kolmogorov forcing 1e-5) + analysis"
+            # a budget that holds about a third of the sessions: admissions evict
+            fp = sorted((s.footprint() for s in srv.sessions), reverse=True)
+            srv.close()
+            tight = fp[0] + sum(fp[1:]) // 3
+            srv = serving.AssimilationServer(specs, budget_bytes=tight, n_slots=8)
+            out["serving_tight_budget"] = srv.run_poisson(args.serving_rate,
+                                                          args.serving_requests // 2, seed=5)
         finally:
             srv.close()
-    if args.precision_steps > 0 or args.batching_problems > 0:
-        del xb, xa, obs
-        torch.cuda.empty_cache()
-    if args.precision_steps > 0:
-        out["precision_form"] = precision_form(L, torch, args.precision_steps)
+            torch.cuda.empty_cache()
     if args.batching_problems > 0:
         out["batching_form"] = batching_form(L, torch, args.batching_problems,
                                              tuple(int(g) for g in args.batching_grids.split(",")),
-                                             args.batching_precision)
+                                             args.batching_precision, args.batching_reps,
+                                             args.batching_tune)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds, args.cpu_cores)
     print(json.dumps(out), flush=True)
 
 

@@ -55,6 +55,7 @@ extern "C" {
 #define LETKF_EBUSY       4  /* plan in use by another call */
 #define LETKF_ENONFINITE  5  /* a non-finite analysis value was produced */
 #define LETKF_ENOTCONV    6  /* eigensolver hit its sweep limit before converging */
+#define LETKF_EIO         7  /* the tuning cache file could not be written */
 
 /* ---- enums ---- */
 /* Localization function G (Sec. II-B, R-localization). */
@@ -90,12 +91,38 @@ typedef struct letkf_problem {
 #define LETKF_FLAG_PHASE_TIMING 1  /* record HIP events around every kernel phase */
 #define LETKF_FLAG_CYCLE        2  /* also allocate the lattice-BGK ping-pong buffer that
                                       letkf_cycle needs (one ensemble per problem) */
+#define LETKF_FLAG_OBS_ON_HOST  4  /* the observation arrays of letkf_io (Algorithm 1's Y^o)
+                                      are host memory: each call checks them on the host
+                                      (LETKF_EINVAL before anything is enqueued) and copies
+                                      them with hipMemcpyAsync on the call's stream into
+                                      buffers the plan allocated for n_obs_max observations.
+                                      The host arrays must stay unchanged until the stream
+                                      has executed the copy (pinned memory makes the copy
+                                      asynchronous; pageable memory is staged before the
+                                      call returns) */
+#define LETKF_FLAG_DETERMINISTIC 8 /* results may depend on nothing but the inputs: the
+                                      observation-cell edge (which sets the summation order
+                                      of the Gram matrix) stays at its default whatever
+                                      letkf_tune measures or the tuning cache holds; only
+                                      settings that leave every bit unchanged (the Gram
+                                      kernel form) are tuned.  Without the flag the results
+                                      are still bitwise reproducible for a fixed setting,
+                                      alone or batched, on any stream */
+#define LETKF_FLAG_GRAPH_CAPTURE 16 /* the plan's analyze / cycle calls will be captured into
+                                      HIP graphs: refused together with PHASE_TIMING (its
+                                      event records cannot be read back from replays).  Every
+                                      call enqueues only kernels and, with OBS_ON_HOST and
+                                      odd n_steps cycles, asynchronous copies: no allocation,
+                                      memset or host synchronization */
 
-/* Plan options (pass NULL for the defaults: no budget, no flags). */
+/* Plan options (pass NULL for the defaults: no budget, no flags, no cache). */
 typedef struct letkf_options {
-  uint64_t hbm_budget_bytes;  /* workspace limit; 0 = no limit */
-  int32_t  flags;             /* LETKF_FLAG_* */
-  int32_t  reserved;
+  uint64_t hbm_budget_bytes;    /* workspace limit; 0 = no limit */
+  int32_t  flags;               /* LETKF_FLAG_* */
+  int32_t  reserved;            /* must be 0 */
+  const char* tune_cache_path;  /* NULL, or a text file of letkf_tune results: letkf_plan
+                                   applies the entry recorded for the same problem list and
+                                   device (if any), letkf_tune records its choice there */
 } letkf_options;
 
 typedef struct letkf_plan_s* letkf_plan_t;
@@ -105,9 +132,11 @@ typedef struct letkf_plan_s* letkf_plan_t;
  *   probs[n_probs]: problem descriptors (host memory, copied).
  *   opt:            may be NULL.
  *   out:            receives the plan handle (set to NULL on error).
- * Returns LETKF_EINVAL (any descriptor out of range, n_probs < 1, out NULL),
- * LETKF_ENOMEM (workspace above hbm_budget_bytes or hipMalloc failure) or
- * LETKF_EDEVICE (no gfx950 device).  Host checks run before any device call.
+ * Returns LETKF_EINVAL (any descriptor out of range, n_probs < 1, out NULL,
+ * unknown flag, reserved != 0, GRAPH_CAPTURE with PHASE_TIMING), LETKF_ENOMEM
+ * (workspace above hbm_budget_bytes or hipMalloc failure) or LETKF_EDEVICE
+ * (no gfx950 device).  Host checks run before any device call.  A tuning
+ * cache that is missing or unreadable is not an error (defaults apply).
  */
 int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options* opt,
                letkf_plan_t* out);
@@ -118,11 +147,11 @@ typedef struct letkf_io {
   int32_t n_obs;            /* 0 <= n_obs <= n_obs_max */
   const double*  xb;        /* device, [k][9][ny][nx] forecast ensemble */
   double*        xa;        /* device, [k][9][ny][nx] analysis; may equal xb */
-  const int32_t* obs_ix;    /* device, [n_obs] lattice x in [0, nx) */
-  const int32_t* obs_iy;    /* device, [n_obs] lattice y in [0, ny) */
-  const int32_t* obs_kind;  /* device, [n_obs] LETKF_OBS_* */
-  const double*  obs_val;   /* device, [n_obs] observed values y^o */
-  const double*  obs_var;   /* device, [n_obs] error variances sigma^2 (R diagonal);
+  const int32_t* obs_ix;    /* [n_obs] lattice x in [0, nx)  (device; host with OBS_ON_HOST) */
+  const int32_t* obs_iy;    /* [n_obs] lattice y in [0, ny) */
+  const int32_t* obs_kind;  /* [n_obs] LETKF_OBS_* */
+  const double*  obs_val;   /* [n_obs] observed values y^o, finite */
+  const double*  obs_var;   /* [n_obs] error variances sigma^2 (R diagonal);
                                > 0, +inf means "ignore this observation" */
 } letkf_io;
 
@@ -130,9 +159,10 @@ typedef struct letkf_io {
  * letkf_analyze -- enqueue n_io analyses on hip_stream (a hipStream_t, or
  * NULL for the null stream).  Asynchronous and stream-ordered; returns after
  * host checks (LETKF_EINVAL: bad problem index, n_obs out of range, NULL
- * pointer with n_obs > 0 or NULL xb/xa).  Device-side observation checks
- * (index range, kind, variance > 0 or +inf, finite value) set the plan status
- * to LETKF_EINVAL and skip the analysis.  In-place (xa == xb) is legal: the
+ * pointer with n_obs > 0 or NULL xb/xa; with OBS_ON_HOST also any invalid
+ * observation record).  Device-side observation checks (index range, kind,
+ * variance > 0 or +inf, finite value) set the plan status to LETKF_EINVAL and
+ * skip the analysis of that problem.  In-place (xa == xb) is legal: the
  * background is fully consumed before any analysis value is written.
  */
 int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream);
@@ -143,7 +173,10 @@ int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip
  * F_x(y) = force_amp * sin(2 pi force_kx y / ny), F_y = 0, added as the
  * source 3 w_i (c_i . F) after relaxation; then one analysis.  The ensemble
  * is advanced and analysed in place: io.xa must equal io.xb.  The plan must
- * have been made with LETKF_FLAG_CYCLE (else LETKF_EINVAL). */
+ * have been made with LETKF_FLAG_CYCLE (else LETKF_EINVAL, unless n_steps is
+ * 0).  If the device finds an invalid observation (status LETKF_EINVAL), the
+ * ensemble is left holding the advanced state of all n_steps steps, not
+ * analysed. */
 typedef struct letkf_cycle_io {
   letkf_io io;
   int32_t  n_steps;    /* >= 0 */
@@ -163,7 +196,11 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
  * keeps the fastest in the plan for later letkf_analyze / letkf_cycle calls.
  * Synchronizes the stream (not usable under graph capture).  On return the
  * outputs hold one analysis made with the chosen setting; out (may be NULL)
- * receives it.  Errors as letkf_analyze, plus LETKF_EDEVICE.
+ * receives it.  With LETKF_FLAG_DETERMINISTIC only the Gram form is timed and
+ * the cell edge keeps its default.  With a tune_cache_path the choice is
+ * recorded in that file under a key of the problem list and device (the
+ * setting still applies if that fails, and LETKF_EIO is returned).  Errors as
+ * letkf_analyze, plus LETKF_EDEVICE.
  */
 typedef struct letkf_tuning {
   int32_t cell;             /* observation-cell edge chosen */
@@ -186,9 +223,12 @@ int letkf_set_tuning(letkf_plan_t plan, const letkf_tuning* t);
 
 /*
  * letkf_status -- device-detected status of the plan's calls since the last
- * letkf_status.  sync != 0 waits for the plan's last stream first (otherwise
- * the value reflects only completed work).  Returns LETKF_OK or the first
- * error code; the status is cleared after reading.
+ * letkf_status.  sync != 0 waits for the plan's last stream first; sync == 0
+ * does not wait for it (the word is read on a stream of the plan's own, so
+ * the value reflects the work completed so far).  Returns LETKF_OK or the
+ * most severe code found (EINVAL, then ENONFINITE, then ENOTCONV); the bits
+ * that were read are cleared (an error raised after the read stays for the
+ * next call).
  */
 int letkf_status(letkf_plan_t plan, int32_t sync);
 

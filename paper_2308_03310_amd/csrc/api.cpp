@@ -14,9 +14,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -49,6 +51,12 @@ struct ProblemWs {
   double* rinv;
   double* bgk;   // lattice-BGK ping-pong buffer (plans made with LETKF_FLAG_CYCLE)
   int* abort_flag;
+  // device copies of host observation arrays (plans made with LETKF_FLAG_OBS_ON_HOST)
+  int32_t* h_ix;
+  int32_t* h_iy;
+  int32_t* h_kind;
+  double* h_val;
+  double* h_var;
 };
 
 // Problems sharing an eigensolver width and precision: the Gram and
@@ -63,6 +71,9 @@ struct ProblemClass {
 };
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+constexpr int kKnownFlags = LETKF_FLAG_PHASE_TIMING | LETKF_FLAG_CYCLE | LETKF_FLAG_OBS_ON_HOST |
+                            LETKF_FLAG_DETERMINISTIC | LETKF_FLAG_GRAPH_CAPTURE;
 
 int check_problem(const letkf_problem& p) {
   if (p.nx < 1 || p.ny < 1 || p.nx > kMaxDim || p.ny > kMaxDim) return LETKF_EINVAL;
@@ -115,6 +126,10 @@ int slab_points(int nb, int kp, int total) {
 
 struct letkf_plan_s {
   int device = 0;
+  int flags = 0;
+  std::string cache_path;           // tuning cache (empty: none)
+  hipStream_t aux = nullptr;        // the plan's own stream: status reads
+  int* host_stat = nullptr;         // pinned host word the status is read into
   std::vector<ProblemWs> probs;
   std::vector<ProblemClass> classes;
   GramArgs* g_one = nullptr;        // device [nprob]: descriptor of each problem
@@ -152,6 +167,10 @@ struct letkf_plan_s {
     allocs.clear();
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     ev.clear();
+    if (aux) (void)hipStreamDestroy(aux);
+    aux = nullptr;
+    if (host_stat) (void)hipHostFree(host_stat);
+    host_stat = nullptr;
   }
 };
 
@@ -176,7 +195,7 @@ void plan_sizes(ProblemWs& w) {
   w.nobs_alloc = p.n_obs_max > 0 ? p.n_obs_max : 1;
 }
 
-uint64_t ws_bytes(const ProblemWs& w, bool cycle) {
+uint64_t ws_bytes(const ProblemWs& w, bool cycle, bool host_obs) {
   const uint64_t no = (uint64_t)w.nobs_alloc;
   const uint64_t ystride =
       w.p.precision == LETKF_PREC_FP64 ? 8 : (w.p.precision == LETKF_PREC_FP32 ? 4 : 2);
@@ -184,6 +203,7 @@ uint64_t ws_bytes(const ProblemWs& w, bool cycle) {
   uint64_t b = state * (cycle ? 2 : 1);
   b += no * 5 * sizeof(int) + no * w.kp * ystride + no * 2 * sizeof(double);
   b += (uint64_t)(3 * max_cells(w) + 1) * sizeof(int);
+  if (host_obs) b += no * (3 * sizeof(int32_t) + 2 * sizeof(double));
   return b;
 }
 
@@ -463,6 +483,133 @@ bool upload_descriptors(letkf_plan_s* pl) {
   return ok;
 }
 
+
+// ---- observations in host memory (LETKF_FLAG_OBS_ON_HOST) ----
+
+// The checks the device makes (k_obs_count), made on the host before anything
+// is enqueued.
+int check_host_obs(const letkf_problem& p, const letkf_io& io) {
+  for (int j = 0; j < io.n_obs; ++j) {
+    const int32_t x = io.obs_ix[j], y = io.obs_iy[j], kd = io.obs_kind[j];
+    const double var = io.obs_var[j], val = io.obs_val[j];
+    const bool var_ok = var > 0.0;                 // false for NaN and <= 0; +inf allowed
+    const bool ignored = var_ok && std::isinf(var);
+    if (!(x >= 0 && x < p.nx && y >= 0 && y < p.ny && kd >= LETKF_OBS_RHO && kd <= LETKF_OBS_V &&
+          var_ok && (ignored || std::isfinite(val))))
+      return LETKF_EINVAL;
+  }
+  return LETKF_OK;
+}
+
+// Copies io's host observation arrays into the problem's device buffers on s
+// and returns io with its observation pointers moved there.
+int stage_host_obs(const ProblemWs& w, const letkf_io& io, hipStream_t s, letkf_io& out) {
+  out = io;
+  if (io.n_obs == 0) return LETKF_OK;
+  const size_t n = (size_t)io.n_obs;
+  const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+  if (hipMemcpyAsync(w.h_ix, io.obs_ix, n * sizeof(int32_t), h2d, s) != hipSuccess ||
+      hipMemcpyAsync(w.h_iy, io.obs_iy, n * sizeof(int32_t), h2d, s) != hipSuccess ||
+      hipMemcpyAsync(w.h_kind, io.obs_kind, n * sizeof(int32_t), h2d, s) != hipSuccess ||
+      hipMemcpyAsync(w.h_val, io.obs_val, n * sizeof(double), h2d, s) != hipSuccess ||
+      hipMemcpyAsync(w.h_var, io.obs_var, n * sizeof(double), h2d, s) != hipSuccess)
+    return LETKF_EDEVICE;
+  out.obs_ix = w.h_ix;
+  out.obs_iy = w.h_iy;
+  out.obs_kind = w.h_kind;
+  out.obs_val = w.h_val;
+  out.obs_var = w.h_var;
+  return LETKF_OK;
+}
+
+// Host checks of a call's observation records (OBS_ON_HOST plans only).
+int check_host_obs_all(const letkf_plan_s* pl, const letkf_io* io, int n_io) {
+  if (!(pl->flags & LETKF_FLAG_OBS_ON_HOST)) return LETKF_OK;
+  for (int i = 0; i < n_io; ++i) {
+    const int rc = check_host_obs(pl->probs[io[i].problem].p, io[i]);
+    if (rc != LETKF_OK) return rc;
+  }
+  return LETKF_OK;
+}
+
+// io as the kernels read it: the caller's, or (OBS_ON_HOST) with the
+// observations copied to the plan's buffers on s.
+int device_ios(const letkf_plan_s* pl, const letkf_io* io, int n_io, hipStream_t s,
+               std::vector<letkf_io>& out) {
+  out.assign(io, io + n_io);
+  if (!(pl->flags & LETKF_FLAG_OBS_ON_HOST)) return LETKF_OK;
+  for (int i = 0; i < n_io; ++i) {
+    const int rc = stage_host_obs(pl->probs[io[i].problem], io[i], s, out[i]);
+    if (rc != LETKF_OK) return rc;
+  }
+  return LETKF_OK;
+}
+
+// ---- tuning cache (letkf_options.tune_cache_path) ----
+// One line per entry: "<key> <cell> <gram_persistent> <ms_per_call>", key =
+// 64-bit FNV-1a of the problem list and the device's architecture and CU
+// count, in hex.  The last line with a key wins.
+
+uint64_t tune_key(const letkf_plan_s* pl) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  for (const ProblemWs& w : pl->probs) mix(&w.p, sizeof(letkf_problem));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) {
+    mix(prop.gcnArchName, std::strlen(prop.gcnArchName));
+    mix(&prop.multiProcessorCount, sizeof(int));
+  }
+  return h;
+}
+
+bool load_tune_cache(const letkf_plan_s* pl, int* cell, int* persistent) {
+  if (pl->cache_path.empty()) return false;
+  FILE* f = std::fopen(pl->cache_path.c_str(), "r");
+  if (!f) return false;
+  const uint64_t key = tune_key(pl);
+  bool found = false;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    unsigned long long k = 0;
+    int c = 0, pe = 0;
+    double ms = 0.0;
+    if (std::sscanf(line, "%llx %d %d %lf", &k, &c, &pe, &ms) == 4 && k == key &&
+        (c == 4 || c == 8 || c == 16) && (pe == 0 || pe == 1)) {
+      *cell = c;
+      *persistent = pe;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+bool save_tune_cache(const letkf_plan_s* pl, int cell, int persistent, double ms) {
+  const uint64_t key = tune_key(pl);
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(pl->cache_path.c_str(), "r")) {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+      unsigned long long k = 0;
+      if (std::sscanf(line, "%llx", &k) == 1 && k == key) continue;
+      keep.emplace_back(line);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = pl->cache_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool ok = true;
+  for (const std::string& l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
+  ok = ok && std::fprintf(f, "%016llx %d %d %.6f\n", (unsigned long long)key, cell, persistent,
+                          ms) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok && std::rename(tmp.c_str(), pl->cache_path.c_str()) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -476,6 +623,7 @@ const char* letkf_strerror(int code) {
     case LETKF_EBUSY: return "plan in use by another call";
     case LETKF_ENONFINITE: return "non-finite analysis value";
     case LETKF_ENOTCONV: return "eigensolver did not converge";
+    case LETKF_EIO: return "tuning cache file could not be written";
     default: return "unknown status";
   }
 }
@@ -484,8 +632,11 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
                letkf_plan_t* out) {
   if (out) *out = nullptr;
   if (!out || !probs || n_probs < 1) return LETKF_EINVAL;
-  if (opt && (opt->flags & ~(LETKF_FLAG_PHASE_TIMING | LETKF_FLAG_CYCLE)) != 0) return LETKF_EINVAL;
-  const bool cycle = opt && (opt->flags & LETKF_FLAG_CYCLE);
+  const int flags = opt ? opt->flags : 0;
+  if ((flags & ~kKnownFlags) != 0 || (opt && opt->reserved != 0)) return LETKF_EINVAL;
+  if ((flags & LETKF_FLAG_GRAPH_CAPTURE) && (flags & LETKF_FLAG_PHASE_TIMING)) return LETKF_EINVAL;
+  const bool cycle = flags & LETKF_FLAG_CYCLE;
+  const bool host_obs = flags & LETKF_FLAG_OBS_ON_HOST;
   for (int i = 0; i < n_probs; ++i) {
     const int rc = check_problem(probs[i]);
     if (rc != LETKF_OK) return rc;
@@ -526,7 +677,7 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     b_doubles = std::max(b_doubles, sl * w.kp);
   }
   uint64_t total = 4096 + (c_doubles + b_doubles) * sizeof(double);
-  for (auto& w : ws) total += ws_bytes(w, cycle);
+  for (auto& w : ws) total += ws_bytes(w, cycle, host_obs);
   if (opt && opt->hbm_budget_bytes && total > opt->hbm_budget_bytes) return LETKF_ENOMEM;
   int dev = 0;
   const int drc = check_device(&dev);
@@ -535,9 +686,13 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
   letkf_plan_s* pl = new (std::nothrow) letkf_plan_s();
   if (!pl) return LETKF_ENOMEM;
   pl->device = dev;
+  pl->flags = flags;
+  if (opt && opt->tune_cache_path) pl->cache_path = opt->tune_cache_path;
   pl->probs = ws;
   pl->classes = classes;
   bool ok = pl->alloc(&pl->stat, 2 + (size_t)n_probs);
+  ok = ok && hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&pl->host_stat, sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int i = 0; ok && i < n_probs; ++i) {
     ProblemWs& w = pl->probs[i];
     const int k = w.p.k;
@@ -558,6 +713,18 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     ok = ok && pl->alloc(&w.cell_count, mc) && pl->alloc(&w.cell_start, mc + 1) &&
          pl->alloc(&w.cell_fill, mc);
     if (cycle) ok = ok && pl->alloc(&w.bgk, (size_t)w.npts * 9 * k);
+    if (host_obs)
+      ok = ok && pl->alloc(&w.h_ix, no) && pl->alloc(&w.h_iy, no) && pl->alloc(&w.h_kind, no) &&
+           pl->alloc(&w.h_val, no) && pl->alloc(&w.h_var, no);
+  }
+  // a setting recorded by an earlier letkf_tune for the same problems and device
+  if (ok) {
+    int cell = kCell, pers = 0;
+    if (load_tune_cache(pl, &cell, &pers)) {
+      if (flags & LETKF_FLAG_DETERMINISTIC) cell = kCell;
+      for (auto& w : pl->probs) set_cell(w, cell);
+      pl->gram_persistent = pers == 1;
+    }
   }
   ok = ok && pl->alloc(&pl->slab_C, (size_t)c_doubles) && pl->alloc(&pl->slab_b, (size_t)b_doubles);
   // descriptors: one per problem, and one table per class
@@ -594,13 +761,17 @@ int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip
     const int rc = check_io(plan, io[i]);
     if (rc != LETKF_OK) return rc;
   }
+  if (check_host_obs_all(plan, io, n_io) != LETKF_OK) return LETKF_EINVAL;
   int expect = 0;
   if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<letkf_io> dio;
+  int rc = device_ios(plan, io, n_io, s, dio);
   std::vector<const double*> src(n_io);
   for (int i = 0; i < n_io; ++i) src[i] = io[i].xb;
-  const int rc = enqueue(plan, io, src.data(), n_io, covers_all_once(plan, io, n_io), s);
+  if (rc == LETKF_OK)
+    rc = enqueue(plan, dio.data(), src.data(), n_io, covers_all_once(plan, io, n_io), s);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;
@@ -616,42 +787,55 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
       return LETKF_EINVAL;
     if (io[i].n_steps > 0 && !plan->probs[io[i].io.problem].bgk) return LETKF_EINVAL;
   }
+  std::vector<letkf_io> ios(n_io);
+  for (int i = 0; i < n_io; ++i) ios[i] = io[i].io;
+  if (check_host_obs_all(plan, ios.data(), n_io) != LETKF_OK) return LETKF_EINVAL;
   int expect = 0;
   if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc = LETKF_OK;
-  std::vector<letkf_io> ios(n_io);
+  std::vector<letkf_io> dio;
+  int rc = device_ios(plan, ios.data(), n_io, s, dio);
   std::vector<const double*> src(n_io);
   for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
     const letkf_cycle_io& c = io[i];
     ProblemWs& w = plan->probs[c.io.problem];
-    // ping-pong between the caller's ensemble and the plan's buffer
-    double* cur = const_cast<double*>(c.io.xb);
+    // Ping-pong between the caller's ensemble and the plan's buffer, arranged
+    // so that the last step writes the caller's ensemble (an odd count starts
+    // from a copy in the buffer): the advanced state is in io.xb whether or
+    // not the analysis runs.
+    double* xb = const_cast<double*>(c.io.xb);
+    double* cur = xb;
     double* nxt = w.bgk;
+    if (c.n_steps % 2 == 1) {
+      const size_t bytes = (size_t)w.npts * 9 * w.p.k * sizeof(double);
+      if (hipMemcpyAsync(w.bgk, xb, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = LETKF_EDEVICE;
+      std::swap(cur, nxt);
+    }
     for (int st = 0; st < c.n_steps && rc == LETKF_OK; ++st) {
       if (launch_bgk(cur, nxt, w.p.k, w.p.nx, w.p.ny, c.tau, c.force_amp, c.force_kx, s) !=
           hipSuccess)
         rc = LETKF_EDEVICE;
       std::swap(cur, nxt);
     }
-    ios[i] = c.io;
-    src[i] = cur;
+    src[i] = xb;
   }
   if (rc == LETKF_OK)
-    rc = enqueue(plan, ios.data(), src.data(), n_io, covers_all_once(plan, ios.data(), n_io), s);
+    rc = enqueue(plan, dio.data(), src.data(), n_io, covers_all_once(plan, ios.data(), n_io), s);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;
 }
 
-int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream,
+int letkf_tune(letkf_plan_t plan, const letkf_io* io_in, int32_t n_io, void* hip_stream,
                letkf_tuning* out) {
-  if (!plan || !io || n_io < 1) return LETKF_EINVAL;
+  if (!plan || !io_in || n_io < 1) return LETKF_EINVAL;
   for (int i = 0; i < n_io; ++i) {
-    const int rc = check_io(plan, io[i]);
+    const int rc = check_io(plan, io_in[i]);
     if (rc != LETKF_OK) return rc;
   }
+  if (check_host_obs_all(plan, io_in, n_io) != LETKF_OK) return LETKF_EINVAL;
   int expect = 0;
   if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
   DeviceGuard guard(plan->device);
@@ -661,6 +845,12 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_st
     plan->busy.store(0);
     return LETKF_EDEVICE;
   }
+  std::vector<letkf_io> dio;
+  if (device_ios(plan, io_in, n_io, s, dio) != LETKF_OK) {
+    plan->busy.store(0);
+    return LETKF_EDEVICE;
+  }
+  const letkf_io* io = dio.data();
   std::vector<const double*> src(n_io);
   for (int i = 0; i < n_io; ++i) src[i] = io[i].xb;
   const bool batched = covers_all_once(plan, io, n_io);
@@ -675,7 +865,9 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_st
   int best_cell = kCell;
   bool best_persist = false;
   bool have = false;
-  for (int ci = 0; ci < 3 && rc == LETKF_OK; ++ci) {
+  // DETERMINISTIC: only the Gram form, which leaves every bit unchanged
+  const bool det = plan->flags & LETKF_FLAG_DETERMINISTIC;
+  for (int ci = det ? 1 : 0; ci < (det ? 2 : 3) && rc == LETKF_OK; ++ci) {
     for (int pi = 0; pi < 2 && rc == LETKF_OK; ++pi) {
       for (auto& w : plan->probs) set_cell(w, kCells[ci]);
       plan->gram_persistent = pi == 1;
@@ -711,12 +903,15 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_st
   if (e1) (void)hipEventDestroy(e1);
   plan->timing = saved_timing;
   plan->last_stream = s;
-  plan->busy.store(0);
   if (rc == LETKF_OK && out) {
     out->cell = best_cell;
     out->gram_persistent = best_persist ? 1 : 0;
     out->ms_per_call = best_ms;
   }
+  if (rc == LETKF_OK && !plan->cache_path.empty() &&
+      !save_tune_cache(plan, best_cell, best_persist ? 1 : 0, best_ms))
+    rc = LETKF_EIO;
+  plan->busy.store(0);
   return rc;
 }
 
@@ -741,10 +936,16 @@ int letkf_status(letkf_plan_t plan, int32_t sync) {
   if (!plan) return LETKF_EINVAL;
   DeviceGuard guard(plan->device);
   if (sync && hipStreamSynchronize(plan->last_stream) != hipSuccess) return LETKF_EDEVICE;
-  int bits = 0;
-  if (hipMemcpy(&bits, plan->stat + 1, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+  // read on the plan's own non-blocking stream (waits for nothing else), then
+  // clear exactly the bits read with an atomic on the device
+  if (hipMemcpyAsync(plan->host_stat, plan->stat + 1, sizeof(int), hipMemcpyDeviceToHost,
+                     plan->aux) != hipSuccess ||
+      hipStreamSynchronize(plan->aux) != hipSuccess)
     return LETKF_EDEVICE;
-  if (bits && hipMemset(plan->stat + 1, 0, sizeof(int)) != hipSuccess) return LETKF_EDEVICE;
+  const int bits = *plan->host_stat;
+  if (bits && (launch_clear_bits(plan->stat + 1, bits, plan->aux) != hipSuccess ||
+               hipStreamSynchronize(plan->aux) != hipSuccess))
+    return LETKF_EDEVICE;
   if (bits & kStatEinval) return LETKF_EINVAL;
   if (bits & kStatNonfinite) return LETKF_ENONFINITE;
   if (bits & kStatNotconv) return LETKF_ENOTCONV;

@@ -172,10 +172,13 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
   const int lane = lane_id();
   // the point is the wavefront's: uniform (scalar registers and loads)
   const int gidx = __builtin_amdgcn_readfirstlane(bm.g0 + pl);
-  const int prob = __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx));
-  const GramArgs g = uniform_copy(bm.g + prob);   // copied once, into scalar registers
+  const int prob = bm.prefix ? __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx))
+                             : 0;
+  // the problem's descriptor, copied once into scalar registers (or the
+  // launch's inline one when there is no table)
+  const GramArgs g = bm.g ? uniform_copy(bm.g + prob) : bm.g_inline;
   if (*g.abort_flag) return;
-  const int pt = gidx - bm.prefix[prob];
+  const int pt = gidx - (bm.prefix ? bm.prefix[prob] : 0);
   const int x = pt % g.nx, y = pt / g.nx;
 
   GramAccLp<KQ, PREC> acc;

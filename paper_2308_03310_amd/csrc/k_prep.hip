@@ -16,6 +16,11 @@ __global__ void k_fill_i32(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// Clears the given bits of a status word (bits raised meanwhile survive).
+__global__ void k_clear_bits(int* p, int bits) {
+  if (threadIdx.x == 0) atomicAnd(p, ~bits);
+}
+
 // Validate each observation record and count it into its cell.
 __global__ void k_obs_count(ObsArgs a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,6 +181,11 @@ __global__ __launch_bounds__(256) void k_obs_operator(ObsArgs a) {
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_bits(int* p, int bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(64), 0, s, p, bits);
   return hipGetLastError();
 }
 

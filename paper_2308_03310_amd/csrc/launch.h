@@ -88,7 +88,7 @@ struct EvdArgs {
 // of one).  Descriptors live in device memory; C and b of the slab are
 // indexed by the slab-local point.
 struct BatchMap {
-  const GramArgs* g;   // [nprob]
+  const GramArgs* g;   // [nprob]; null: one problem described by g_inline
   const EvdArgs* e;    // [nprob]; null: one problem described by e_inline
   const int* prefix;   // [nprob + 1] first global point of each problem; null: {0}
   int nprob;
@@ -96,6 +96,7 @@ struct BatchMap {
   double* C;           // [n][NB][256]
   double* b;           // [n][KP]
   int* queue;          // [kQueueSlots] work counters of the persistent launches
+  GramArgs g_inline;
   EvdArgs e_inline;
 };
 
@@ -142,6 +143,7 @@ __device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gi
 
 // --- launchers (return hipError_t of the launch) ---
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
+hipError_t launch_clear_bits(int* p, int bits, hipStream_t s);
 hipError_t launch_bin(const ObsArgs& a, hipStream_t s);
 hipError_t launch_transpose_in(const double* xb, double* xt, int k, int npts, const int* abort_flag,
                                hipStream_t s);

@@ -1,10 +1,15 @@
 """Python binding of libletkf.so (include/letkf.h): argument marshalling only.
 
 Every function here has the name of the C entry point it calls.  Tensors are
-torch tensors on the plan's device (float64 / int32, contiguous); streams
-default to torch's current stream.  All arithmetic runs in the library's
-gfx950 kernels: if the library is missing, loading raises instead of falling
-back to anything else.
+torch tensors on the plan's device (float64 / int32, contiguous); with
+LETKF_FLAG_OBS_ON_HOST the observation arrays are host tensors instead.
+Streams default to torch's current stream.  All arithmetic runs in the
+library's gfx950 kernels: if the library is missing, loading raises instead
+of falling back to anything else.
+
+Before a call reaches the library, each letkf_io is checked against the
+plan's problem descriptors: a tensor of the wrong size, dtype or device would
+otherwise make the kernels read or write outside it.
 """
 from __future__ import annotations
 
@@ -18,13 +23,16 @@ LIB_PATH = os.path.join(_HERE, "libletkf.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "letkf.h")
 
 LETKF_OK, LETKF_EINVAL, LETKF_ENOMEM, LETKF_EDEVICE = 0, 1, 2, 3
-LETKF_EBUSY, LETKF_ENONFINITE, LETKF_ENOTCONV = 4, 5, 6
+LETKF_EBUSY, LETKF_ENONFINITE, LETKF_ENOTCONV, LETKF_EIO = 4, 5, 6, 7
 LETKF_LOC_GAUSS, LETKF_LOC_GC, LETKF_LOC_NONE = 0, 1, 2
 LETKF_PREC_FP64, LETKF_PREC_FP32, LETKF_PREC_BF16 = 0, 1, 2
 LETKF_OBS_RHO, LETKF_OBS_U, LETKF_OBS_V = 0, 1, 2
 LETKF_MAX_K = 64
 LETKF_FLAG_PHASE_TIMING = 1
 LETKF_FLAG_CYCLE = 2
+LETKF_FLAG_OBS_ON_HOST = 4
+LETKF_FLAG_DETERMINISTIC = 8
+LETKF_FLAG_GRAPH_CAPTURE = 16
 PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose")
 
 
@@ -36,7 +44,7 @@ class letkf_problem(ctypes.Structure):
 
 class letkf_options(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("tune_cache_path", ctypes.c_char_p)]
 
 
 class letkf_io(ctypes.Structure):
@@ -58,6 +66,8 @@ class letkf_cycle_io(ctypes.Structure):
 
 
 _lib = None
+# plan handle -> (problem descriptors, flags), for the argument checks
+_plans: dict = {}
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -115,13 +125,15 @@ def _check(code: int, where: str) -> int:
     return code
 
 
-def _ptr(t, dtype=None) -> int:
+def _ptr(t, dtype=None, host: bool = False) -> int:
     if t is None:
         return 0
     import torch
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"expected {dtype}, got {t.dtype}")
-    if not t.is_cuda:
+    if host and t.is_cuda:
+        raise TypeError("expected a host tensor (LETKF_FLAG_OBS_ON_HOST)")
+    if not host and not t.is_cuda:
         raise TypeError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
@@ -148,50 +160,95 @@ def make_problem(nx, ny, k, n_obs_max, loc_len, infl, loc=LETKF_LOC_GAUSS,
 
 
 def letkf_plan(problems: Sequence[letkf_problem], hbm_budget_bytes: int = 0, flags: int = 0,
-               raise_on_error: bool = True):
+               raise_on_error: bool = True, tune_cache_path: Optional[str] = None):
     """Returns the plan handle (int), or (code, None) when raise_on_error is False."""
     lib = load_library()
     arr = (letkf_problem * len(problems))(*problems) if len(problems) else None
-    opt = letkf_options(int(hbm_budget_bytes), int(flags), 0)
+    path = tune_cache_path.encode() if tune_cache_path else None
+    opt = letkf_options(int(hbm_budget_bytes), int(flags), 0, path)
     h = ctypes.c_void_p()
     rc = lib.letkf_plan(arr, len(problems), ctypes.byref(opt), ctypes.byref(h))
+    if rc == LETKF_OK and h.value:
+        _plans[h.value] = ([letkf_problem(p.nx, p.ny, p.k, p.n_obs_max, p.loc_len, p.infl, p.loc,
+                                          p.precision) for p in problems], int(flags))
     if not raise_on_error:
         return rc, h.value
     _check(rc, "letkf_plan")
     return h.value
 
 
-def make_io(problem: int, xb, xa, obs=None) -> letkf_io:
-    """obs: dict or tuple of device tensors (ix, iy, kind int32; val, var float64)."""
+def make_io(problem: int, xb, xa, obs=None, obs_on_host: bool = False) -> letkf_io:
+    """obs: dict or tuple of tensors (ix, iy, kind int32; val, var float64) on
+    the device, or on the host for a plan made with LETKF_FLAG_OBS_ON_HOST
+    (obs_on_host=True).  The element counts are kept with the descriptor and
+    checked against the plan's problem when the call is made."""
     import torch
     if obs is None:
-        n, p = 0, (0, 0, 0, 0, 0)
+        n, p, counts = 0, (0, 0, 0, 0, 0), ()
     else:
         if isinstance(obs, dict):
             obs = (obs["ix"], obs["iy"], obs["kind"], obs["val"], obs["var"])
         ix, iy, kd, val, var = obs
         n = int(ix.numel())
-        p = (_ptr(ix, torch.int32), _ptr(iy, torch.int32), _ptr(kd, torch.int32),
-             _ptr(val, torch.float64), _ptr(var, torch.float64))
-    return letkf_io(int(problem), n, _ptr(xb, torch.float64), _ptr(xa, torch.float64), *p)
+        h = bool(obs_on_host)
+        p = (_ptr(ix, torch.int32, h), _ptr(iy, torch.int32, h), _ptr(kd, torch.int32, h),
+             _ptr(val, torch.float64, h), _ptr(var, torch.float64, h))
+        counts = tuple(int(t.numel()) for t in (ix, iy, kd, val, var))
+    io = letkf_io(int(problem), n, _ptr(xb, torch.float64), _ptr(xa, torch.float64), *p)
+    io._numel = (int(xb.numel()), int(xa.numel())) + counts
+    io._obs_on_host = bool(obs_on_host) and obs is not None
+    return io
+
+
+def _validate(plan: int, io: letkf_io) -> None:
+    """Sizes of io's arrays against the plan's problem (raises ValueError)."""
+    entry = _plans.get(plan)
+    if entry is None:
+        return
+    probs, flags = entry
+    if not 0 <= io.problem < len(probs):
+        raise ValueError(f"problem index {io.problem} out of range ({len(probs)} problems)")
+    p = probs[io.problem]
+    counts = getattr(io, "_numel", None)
+    if counts is None:
+        raise ValueError("letkf_io must be made with make_io (its array sizes are checked)")
+    state = p.nx * p.ny * 9 * p.k
+    if counts[0] != state or counts[1] != state:
+        raise ValueError(f"xb / xa hold {counts[0]} / {counts[1]} values, problem {io.problem} "
+                         f"needs {state} ([{p.k}][9][{p.ny}][{p.nx}])")
+    if any(c != io.n_obs for c in counts[2:]):
+        raise ValueError(f"observation arrays differ in length: {counts[2:]}")
+    if io.n_obs > p.n_obs_max:
+        raise ValueError(f"{io.n_obs} observations, the plan allows {p.n_obs_max}")
+    host = bool(flags & LETKF_FLAG_OBS_ON_HOST)
+    if io.n_obs > 0 and io._obs_on_host != host:
+        raise ValueError("observation arrays must be " + ("host" if host else "device") +
+                         " tensors for this plan")
 
 
 def letkf_analyze(plan: int, ios: Iterable[letkf_io], stream=None) -> int:
     ios = list(ios)
+    for io in ios:
+        _validate(plan, io)
     arr = (letkf_io * len(ios))(*ios)
     return _check(load_library().letkf_analyze(plan, arr, len(ios), _stream(stream)),
                   "letkf_analyze")
 
 
 def make_cycle_io(problem: int, x, obs=None, n_steps: int = 50, tau: float = 0.52,
-                  force_amp: float = 1e-5, force_kx: int = 4) -> letkf_cycle_io:
+                  force_amp: float = 1e-5, force_kx: int = 4,
+                  obs_on_host: bool = False) -> letkf_cycle_io:
     """In-place cycle descriptor for ensemble x (advanced, then analysed)."""
-    return letkf_cycle_io(make_io(problem, x, x, obs), int(n_steps), int(force_kx), float(tau),
-                          float(force_amp))
+    io = make_io(problem, x, x, obs, obs_on_host)
+    c = letkf_cycle_io(io, int(n_steps), int(force_kx), float(tau), float(force_amp))
+    c._io = io
+    return c
 
 
 def letkf_cycle(plan: int, ios: Iterable[letkf_cycle_io], stream=None) -> int:
     ios = list(ios)
+    for c in ios:
+        _validate(plan, getattr(c, "_io", c.io))
     arr = (letkf_cycle_io * len(ios))(*ios)
     return _check(load_library().letkf_cycle(plan, arr, len(ios), _stream(stream)), "letkf_cycle")
 
@@ -201,6 +258,7 @@ def letkf_status(plan: int, sync: bool = True) -> int:
 
 
 def letkf_plan_destroy(plan: Optional[int]) -> int:
+    _plans.pop(plan, None)
     return load_library().letkf_plan_destroy(plan)
 
 
@@ -223,6 +281,11 @@ def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
     """a [batch, k, k] float64 -> lam [batch, k], vec [batch, k, k] (columns)."""
     import torch
     batch, k = int(a.shape[0]), int(a.shape[-1])
+    if a.numel() != batch * k * k or lam.numel() != batch * k or vec.numel() != batch * k * k:
+        raise ValueError(f"eigh_batched: a {tuple(a.shape)}, lam {tuple(lam.shape)}, "
+                         f"vec {tuple(vec.shape)} do not fit batch {batch}, k {k}")
+    if status is not None and status.numel() < 1:
+        raise ValueError("eigh_batched: status needs one int32")
     return _check(load_library().letkf_eigh_batched(
         _ptr(a, torch.float64), batch, k, _ptr(lam, torch.float64), _ptr(vec, torch.float64),
         _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
@@ -232,6 +295,8 @@ def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
 def letkf_tune(plan: int, ios: Iterable[letkf_io], stream=None) -> dict:
     """Autotune the plan's launch settings on these analyses; returns the setting kept."""
     ios = list(ios)
+    for io in ios:
+        _validate(plan, io)
     arr = (letkf_io * len(ios))(*ios)
     t = letkf_tuning()
     _check(load_library().letkf_tune(plan, arr, len(ios), _stream(stream), ctypes.byref(t)),

@@ -14,7 +14,11 @@ Scheduling:
 * every other ready request is dispatched at once to a free stream slot, so
   requests that arrive while others run overlap with them on the device;
 * completion is observed through per-request events; latency = completion
-  time - arrival time (host clock).
+  time - arrival time (host clock);
+* once a cycle's event has fired, the session plan's device status is read
+  (without waiting on anything else) and kept on the request: a cycle that
+  found an invalid observation, a non-finite value or an unconverged
+  eigensolve is counted as failed, not served.
 
 Each session owns all of its device memory, so a session's results are the
 same alone and in any mix (checked by a GPU test, bitwise).
@@ -105,6 +109,11 @@ class Session:
         io = L.make_cycle_io(0, self.x, self.obs, s.n_steps, s.tau, s.force_amp, s.force_kx)
         L.letkf_cycle(self.plan, [io], stream)
 
+    def status(self) -> int:
+        """Device status of the session's cycles since the last read; the
+        caller has seen the cycle's completion event, so nothing is waited on."""
+        return L.letkf_status(self.plan, sync=False)
+
 
 @dataclasses.dataclass
 class Request:
@@ -113,6 +122,7 @@ class Request:
     t_arrive: float
     t_dispatch: float = 0.0
     t_done: float = 0.0
+    status: int = -1          # LETKF_* code of the cycle once done
 
 
 class AssimilationServer:
@@ -181,6 +191,7 @@ class AssimilationServer:
             req, ev, sess = self.running[slot]
             if ev.query():
                 req.t_done = time.perf_counter()
+                req.status = sess.status()
                 sess.busy = False
                 sess.last_used = req.t_done
                 sess.cycles_done += 1
@@ -214,16 +225,24 @@ class AssimilationServer:
                 i += 1
             self.step()
         t1 = time.perf_counter()
-        lat = np.array([r.t_done - r.t_arrive for r in self.done[-n_requests:]]) * 1e3
+        done = self.done[-n_requests:]
+        ok = [r for r in done if r.status == L.LETKF_OK]
+        lat = np.array([r.t_done - r.t_arrive for r in ok]) * 1e3
         points = sum(self.sessions[r.sid].spec.wl.nx * self.sessions[r.sid].spec.wl.ny
-                     for r in self.done[-n_requests:])
+                     for r in ok)
+        codes: Dict[str, int] = {}
+        for r in done:
+            if r.status != L.LETKF_OK:
+                name = L.letkf_strerror(r.status) if r.status >= 0 else "no status"
+                codes[name] = codes.get(name, 0) + 1
+        pct = lambda q: round(float(np.percentile(lat, q)), 3) if len(lat) else None
         return {"requests": n_requests, "offered_rate_hz": rate_hz,
                 "wall_s": round(t1 - t0, 3),
-                "throughput_cycles_per_s": round(n_requests / (t1 - t0), 2),
+                "served": len(ok), "failed": len(done) - len(ok), "failures": codes,
+                "throughput_cycles_per_s": round(len(ok) / (t1 - t0), 2),
                 "throughput_analyses_per_s": round(points / (t1 - t0), 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "mean_ms": round(float(lat.mean()), 3),
+                "p50_ms": pct(50), "p99_ms": pct(99),
+                "mean_ms": round(float(lat.mean()), 3) if len(lat) else None,
                 "admissions": self.admissions, "evictions": self.evictions,
                 "slots": len(self.streams), "budget_bytes": self.budget}
 
@@ -235,17 +254,21 @@ class AssimilationServer:
         self.used = 0
 
 
-def default_specs(n_sessions: int = 16, seed: int = 4) -> List[SessionSpec]:
-    """Session shapes mixing the analysis workloads: 256^2/k=32 (stride 2,
-    L=8) and smaller lattices with k in {16, 32, 64} (L 4-16, sigma
-    0.002-0.01, observation strides 2-4)."""
-    rng = np.random.default_rng(seed)
-    shapes = [(256, 32, 2, 8.0), (64, 16, 2, 4.0), (128, 32, 2, 6.0), (128, 16, 4, 8.0),
-              (64, 64, 2, 4.0), (256, 16, 4, 12.0)]
+def default_specs(n_sessions: int = 12, seed: int = 4, with_large: bool = True) -> List[SessionSpec]:
+    """Sessions mixing the shapes of the three analysis workloads: one of the
+    1024^2, k = 64 precision workload (FP32 form), two of the 256^2, k = 32
+    FP64 workload (stride 2, L = 8, each with its own seed), and the rest
+    drawn by the mixed-batch recipe (lattices 64^2-512^2, k in {16, 32, 64},
+    random masks with clustered gaps, L 4-16, sigma 0.002-0.01; FP32 form).
+    with_large=False leaves out the 1024^2 session."""
     out = []
-    for i in range(n_sessions):
-        n, k, st, Lr = shapes[i % len(shapes)] if i < len(shapes) else shapes[int(rng.integers(len(shapes)))]
-        sigma = float(rng.uniform(0.002, 0.01))
-        wl = synth.Workload(f"s{i}_{n}_k{k}", n, n, k, st, sigma, Lr, 1.1, 100 + i)
+    if with_large:
+        big = dataclasses.replace(synth.WORKLOADS["grid1024_k64"], name="s_grid1024_k64", seed=400)
+        out.append(SessionSpec(big.name, big, precision=L.LETKF_PREC_FP32))
+    for j in range(2):
+        wl = dataclasses.replace(synth.WORKLOADS["grid256_k32"], name=f"s_grid256_k32_{j}",
+                                 seed=410 + j)
         out.append(SessionSpec(wl.name, wl))
-    return out
+    for wl in synth.batching_workloads(max(n_sessions - len(out), 0), seed=seed):
+        out.append(SessionSpec(f"s_{wl.name}", wl, precision=L.LETKF_PREC_FP32))
+    return out[:n_sessions]

@@ -74,12 +74,9 @@ def equilibrium(rho: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
     return _WQ[:, None, None] * rho[..., None, :, :] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
 
 
-def random_mode_velocity(rng: np.random.Generator, nx: int, ny: int, kmax: int = 8):
-    """Divergence-free velocity from a random-mode streamfunction, |kappa| <= kmax.
-
-    Returns (u, v), each [ny, nx], unnormalised.
-    """
-    spec = np.zeros((ny, nx), dtype=np.complex128)
+def _fill_modes(rng: np.random.Generator, spec: np.ndarray, nx: int, ny: int, kmax: int):
+    """Random amplitudes and phases of the modes 0 < |kappa| <= kmax (one of
+    each +-kappa pair), added into the spectrum array."""
     for ky in range(-kmax, kmax + 1):
         for kx in range(-kmax, kmax + 1):
             if kx * kx + ky * ky == 0 or kx * kx + ky * ky > kmax * kmax:
@@ -89,6 +86,15 @@ def random_mode_velocity(rng: np.random.Generator, nx: int, ny: int, kmax: int =
             a = rng.standard_normal()
             ph = rng.uniform(0.0, 2.0 * np.pi)
             spec[ky % ny, kx % nx] += a * np.exp(1j * ph)
+
+
+def random_mode_velocity(rng: np.random.Generator, nx: int, ny: int, kmax: int = 8):
+    """Divergence-free velocity from a random-mode streamfunction, |kappa| <= kmax.
+
+    Returns (u, v), each [ny, nx], unnormalised.
+    """
+    spec = np.zeros((ny, nx), dtype=np.complex128)
+    _fill_modes(rng, spec, nx, ny, kmax)
     kxs = np.fft.fftfreq(nx, 1.0 / nx)[None, :]
     kys = np.fft.fftfreq(ny, 1.0 / ny)[:, None]
     scale = nx * ny
@@ -124,6 +130,13 @@ def make_problem(wl: Workload, seed: Optional[int] = None, dtype=np.float64) -> 
         sp = 0.01 / np.sqrt(0.5 * np.mean(up * up + vp * vp))
         rho = 1.0 + 1e-3 * rng.standard_normal((ny, nx))
         xb[m] = equilibrium(rho, ut + sp * up, vt + sp * vp)
+    return _observations(rng, wl, ut, vt, xb)
+
+
+def _observations(rng: np.random.Generator, wl: Workload, ut, vt, xb) -> Problem:
+    """The observation list of a workload from the truth velocity (the draws
+    that follow the ensemble's in the generator)."""
+    nx, ny = wl.nx, wl.ny
     if wl.density > 0.0:
         mask = obs_mask(rng, nx, ny, wl.density, wl.n_gaps, wl.gap_radius)
         iy, ix = np.nonzero(mask)
@@ -143,6 +156,46 @@ def make_problem(wl: Workload, seed: Optional[int] = None, dtype=np.float64) -> 
     var = np.full(val.shape, wl.sigma ** 2)
     return Problem(wl, xb, obs_ix.astype(np.int32), obs_iy.astype(np.int32),
                    obs_kind.astype(np.int32), val.astype(np.float64), var, ut, vt)
+
+
+def make_problem_device(wl: Workload, device, seed: Optional[int] = None):
+    """make_problem with the background ensemble built on a torch device: the
+    same draws from the same generator, in the same order, with the inverse
+    FFTs and the equilibrium evaluated there (so the members never pass
+    through host memory).  The inputs equal make_problem's up to the rounding
+    of the FFTs.  Returns (xb device tensor [k, 9, ny, nx] float64, Problem
+    whose xb is None)."""
+    import torch
+    rng = np.random.default_rng(wl.seed if seed is None else seed)
+    nx, ny, k = wl.nx, wl.ny, wl.k
+    kxs = torch.fft.fftfreq(nx, 1.0 / nx, dtype=torch.float64, device=device)[None, :]
+    kys = torch.fft.fftfreq(ny, 1.0 / ny, dtype=torch.float64, device=device)[:, None]
+    cx = torch.tensor(_CX, dtype=torch.float64, device=device)[:, None, None]
+    cy = torch.tensor(_CY, dtype=torch.float64, device=device)[:, None, None]
+    wq = torch.tensor(_WQ, dtype=torch.float64, device=device)[:, None, None]
+
+    def velocity():
+        spec = np.zeros((ny, nx), dtype=np.complex128)
+        _fill_modes(rng, spec, nx, ny, 8)
+        sp = torch.from_numpy(spec).to(device)
+        u = torch.fft.ifft2(sp * (1j * 2 * np.pi * kys / ny)).real * (nx * ny)
+        v = -torch.fft.ifft2(sp * (1j * 2 * np.pi * kxs / nx)).real * (nx * ny)
+        return u, v
+
+    ut, vt = velocity()
+    s = 0.05 / torch.sqrt(torch.max(ut * ut + vt * vt))
+    ut, vt = ut * s, vt * s
+    xb = torch.empty((k, 9, ny, nx), dtype=torch.float64, device=device)
+    for m in range(k):
+        up, vp = velocity()
+        sp = 0.01 / torch.sqrt(0.5 * torch.mean(up * up + vp * vp))
+        rho = 1.0 + 1e-3 * torch.from_numpy(rng.standard_normal((ny, nx))).to(device)
+        u, v = ut + sp * up, vt + sp * vp
+        cu = cx * u + cy * v
+        xb[m] = wq * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (u * u + v * v))
+    truth = (ut.cpu().numpy(), vt.cpu().numpy())
+    prob = _observations(rng, wl, truth[0], truth[1], None)
+    return xb, prob
 
 
 def obs_mask(rng: np.random.Generator, nx: int, ny: int, density: float, n_gaps: int,

@@ -28,11 +28,11 @@ def test_exports_every_declared_function(lib):
 
 def test_strerror_covers_codes(lib):
     seen = set()
-    for c in range(7):
+    for c in range(8):
         s = L.letkf_strerror(c)
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 7
+    assert len(seen) == 8
     assert L.letkf_strerror(99) == "unknown status"
 
 
@@ -61,6 +61,46 @@ def test_plan_rejects_bad_enums_and_counts(lib):
     assert lib.letkf_plan(None, 1, None, ctypes.byref(h)) == L.LETKF_EINVAL
     p = L.make_problem(**GOOD)
     assert lib.letkf_plan(ctypes.byref(p), 1, None, None) == L.LETKF_EINVAL
+
+
+def test_plan_rejects_bad_options(lib):
+    """Unknown flags, a nonzero reserved field and GRAPH_CAPTURE together
+    with PHASE_TIMING are refused on the host, before any device call."""
+    p = L.make_problem(**GOOD)
+    for flags in (32, 1 << 20, -1, L.LETKF_FLAG_GRAPH_CAPTURE | L.LETKF_FLAG_PHASE_TIMING):
+        rc, h = L.letkf_plan([p], flags=flags, raise_on_error=False)
+        assert rc == L.LETKF_EINVAL and h is None, flags
+    opt = L.letkf_options(0, 0, 1, None)
+    h = ctypes.c_void_p()
+    assert lib.letkf_plan(ctypes.byref(p), 1, ctypes.byref(opt), ctypes.byref(h)) == L.LETKF_EINVAL
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    """Every struct of the header as the binding lays it out: size and field
+    offsets equal to what the host C compiler gives them (gcc on a probe that
+    includes the header)."""
+    import os
+    import subprocess
+    structs = [L.letkf_problem, L.letkf_options, L.letkf_io, L.letkf_cycle_io, L.letkf_tuning]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "letkf.h"', 'int main(void) {']
+    for st in structs:
+        n = st.__name__
+        lines.append(f'  printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    inc = os.path.join(os.path.dirname(L.HEADER))
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.split("\n") if l)
+    for st in structs:
+        n = st.__name__
+        assert int(out[n]) == ctypes.sizeof(st), n
+        for f, _ in st._fields_:
+            assert int(out[f"{n}.{f}"]) == getattr(st, f).offset, (n, f)
 
 
 def test_budget_checked_before_device(lib):

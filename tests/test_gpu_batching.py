@@ -3,49 +3,77 @@ different lattice sizes, ensemble sizes, localization lengths, error
 variances and random observation masks with clustered gaps (local
 observation counts from 0 to thousands), analysed in one call; and the
 launch settings the autotuner chooses between (observation-cell edge, grid
-or persistent Gram kernels)."""
+or persistent Gram kernels).
+
+Two batches: 24 draws of the recipe on 64^2 and 128^2 lattices, and five
+problems of the full 256-problem recipe (seed 3) on 256^2 and 512^2 lattices
+-- the largest windows (L up to 15), densest masks (up to 45 %) and k = 64.
+Each runs in the FP64 form (oracle bar 1e-10) and the FP32 form (1e-5), and
+the batched call must equal one call per problem bitwise."""
 import numpy as np
 import pytest
 
 from oracle import letkf_oracle as orc
 from paper_2308_03310_amd import letkf as L
 from paper_2308_03310_amd import synth
+from _parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
-N_PROBLEMS = 24
+N_SMALL = 24
+# indices into the full recipe's draws: (512^2, k 64, L 11.8, 18 %),
+# (512^2, k 32, L 12.4, 44 %), (256^2, k 32, L 13.3, 37 %), (256^2, k 64,
+# L 14.9, 32 %), (512^2, k 16, L 7.6, 45 %)
+LARGE_PICK = (3, 10, 5, 54, 4)
+TOL = {L.LETKF_PREC_FP64: 1e-10, L.LETKF_PREC_FP32: 1e-5}
 
 
-@pytest.fixture(scope="module")
-def batch(device):
+def _items(wls):
     import torch
-    wls = synth.batching_workloads(N_PROBLEMS, seed=3, grids=(64, 128))
-    items, probs, ios = [], [], []
-    for i, wl in enumerate(wls):
+    items = []
+    for wl in wls:
         p = synth.make_problem(wl)
         f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
         obs = (f(p.obs_ix, torch.int32), f(p.obs_iy, torch.int32), f(p.obs_kind, torch.int32),
                f(p.obs_val, torch.float64), f(p.obs_var, torch.float64))
         xb = f(p.xb, torch.float64)
-        xa = torch.empty_like(xb)
-        items.append((p, xb, xa, obs))
-        probs.append(L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl))
-        ios.append(L.make_io(i, xb, xa, obs))
+        items.append((p, xb, torch.empty_like(xb), obs))
     print(f"{len(wls)} problems: grids {sorted({w.nx for w in wls})}, "
           f"k {sorted({w.k for w in wls})}, obs {min(len(it[0].obs_ix) for it in items)}-"
           f"{max(len(it[0].obs_ix) for it in items)}", flush=True)
-    return items, probs, ios
+    return items
+
+
+@pytest.fixture(scope="module")
+def small_batch(device):
+    return _items(synth.batching_workloads(N_SMALL, seed=3, grids=(64, 128)))
+
+
+@pytest.fixture(scope="module")
+def large_batch(device):
+    wls = synth.batching_workloads(256, seed=3)
+    return _items([wls[i] for i in LARGE_PICK])
+
+
+def _probs_ios(items, prec):
+    probs = [L.make_problem(p.wl.nx, p.wl.ny, p.wl.k, len(p.obs_ix), p.wl.L, p.wl.infl,
+                            precision=prec) for (p, _, _, _) in items]
+    ios = [L.make_io(i, xb, xa, obs) for i, (_, xb, xa, obs) in enumerate(items)]
+    return probs, ios
 
 
 def _outputs(items):
     return [xa.cpu().numpy() for (_, _, xa, _) in items]
 
 
-def test_mixed_batch_equals_alone_and_oracle(batch):
-    items, probs, ios = batch
+@pytest.mark.parametrize("prec", [L.LETKF_PREC_FP64, L.LETKF_PREC_FP32])
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_mixed_batch_equals_alone_and_oracle(request, which, prec):
+    items = request.getfixturevalue(f"{which}_batch")
+    probs, ios = _probs_ios(items, prec)
     plan = L.letkf_plan(probs)
     try:
-        print("one batched call over every problem", flush=True)
+        print(f"{which} batch, precision {prec}: one batched call over every problem", flush=True)
         L.letkf_analyze(plan, ios)
         assert L.letkf_status(plan) == L.LETKF_OK
         batched = _outputs(items)
@@ -58,21 +86,22 @@ def test_mixed_batch_equals_alone_and_oracle(batch):
         L.letkf_plan_destroy(plan)
     for i in range(len(items)):
         assert np.array_equal(batched[i], alone[i]), i
-    for i in (0, 3, 7, 12, 18, 23):
+    check = range(len(items)) if which == "large" else (0, 3, 7, 12, 18, 23)
+    for i in check:
         p = items[i][0]
         wl = p.wl
-        pts = synth.sample_points(wl.nx, wl.ny, 4, seed=20 + i)
+        pts = synth.sample_points(wl.nx, wl.ny, 6 if which == "large" else 4, seed=20 + i)
         ref = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
                            wl.infl).run(pts)
         got = np.stack([batched[i][:, :, q // wl.nx, q % wl.nx] for q in pts])
-        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        print(f"  problem {i} ({wl.nx}^2, k={wl.k}, L={wl.L:.1f}, {len(p.obs_ix)} obs): "
-              f"rel-L2 {err:.2e}", flush=True)
-        assert err <= 1e-10, i
+        xb = np.stack([p.xb[:, :, q // wl.nx, q % wl.nx] for q in pts])
+        assert_parity(got, ref, TOL[prec], xb, None,
+                      f"problem {i} ({wl.nx}^2, k={wl.k}, L={wl.L:.1f}, {len(p.obs_ix)} obs)")
 
 
-def test_tuning_settings_and_autotuner(batch):
-    items, probs, ios = batch
+def test_tuning_settings_and_autotuner(small_batch):
+    items = small_batch
+    probs, ios = _probs_ios(items, L.LETKF_PREC_FP64)
     plan = L.letkf_plan(probs)
     try:
         res = {}

@@ -79,3 +79,29 @@ def test_cycle_needs_flag_and_inplace(device):
             L.letkf_cycle(plan, [io])
     finally:
         L.letkf_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("n_steps", [1, 2, 5])
+def test_invalid_observation_keeps_the_advance(device, n_steps):
+    """A cycle whose observations hold an invalid record reports LETKF_EINVAL
+    and leaves the ensemble at the model advance of all n_steps steps (odd
+    and even counts alike), unanalysed."""
+    import torch
+    wl = synth.Workload("cycbad", 24, 20, 8, 2, 0.005, 3.0, 1.1, 23)
+    p = synth.make_problem(wl)
+    print(f"cycle 24x20 k=8 n_steps={n_steps} with an invalid observation", flush=True)
+    var = p.obs_var.copy()
+    var[5] = -1.0
+    obs = (_dev(p.obs_ix, torch.int32), _dev(p.obs_iy, torch.int32), _dev(p.obs_kind, torch.int32),
+           _dev(p.obs_val, torch.float64), _dev(var, torch.float64))
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl)],
+                        flags=L.LETKF_FLAG_CYCLE)
+    try:
+        x = _dev(p.xb, torch.float64)
+        L.letkf_cycle(plan, [L.make_cycle_io(0, x, obs, n_steps, 0.52, 1e-5, 4)])
+        assert L.letkf_status(plan) == L.LETKF_EINVAL
+        got = x.cpu().numpy()
+    finally:
+        L.letkf_plan_destroy(plan)
+    ref = lbm.advance(p.xb, n_steps, 0.52, 1e-5, 4)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
