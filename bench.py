@@ -238,7 +238,7 @@ def batching_form(L, torch, n: int, grids, precision: str, reps: int, tune: bool
     wls = synth.batching_workloads(n, seed=3, grids=grids)
     probs, ios, keep, n_obs = [], [], [], []
     for i, wl in enumerate(wls):
-        if i % 32 == 0:
+        if i % 8 == 0:
             print(f"batching form: generating problem {i} of {n}", file=sys.stderr, flush=True)
         xb, p = synth.make_problem_device(wl, dev)
         obs = dev_obs(torch, p, dev)
@@ -267,7 +267,9 @@ def batching_form(L, torch, n: int, grids, precision: str, reps: int, tune: bool
         return e0.elapsed_time(e1) / reps
 
     try:
+        print("batching form: timing one batched call", file=sys.stderr, flush=True)
         ms_batched = timed([ios])
+        print("batching form: timing one call per problem", file=sys.stderr, flush=True)
         ms_single = timed([[io] for io in ios])
         out = {"problems": n, "grids": list(grids), "precision": precision, "grid_points": points,
                "obs_per_problem": [min(n_obs), max(n_obs)], "reps": reps}
@@ -289,9 +291,13 @@ def batching_form(L, torch, n: int, grids, precision: str, reps: int, tune: bool
     return out
 
 
+_ORACLE = None     # the oracle's Analysis, inherited by the forked workers
+
+
 def _oracle_worker(args):
-    an, pts, nx, seconds = args
+    pts, nx, seconds = args
     from threadpoolctl import threadpool_limits
+    an = _ORACLE
     done = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -308,17 +314,25 @@ def cpu_baseline(wl, p, seconds: float, max_cores: int):
     """The oracle, as it is, on a bounded sample of the workload's grid points:
     one process with one BLAS thread, then one such process per host core
     (forked after the forecast observations are computed, so every process
-    evaluates points of the same analysis)."""
+    evaluates points of the same analysis; the workers inherit it rather than
+    receive a copy).  Runs before the GPU is initialised, so the forks carry
+    no device state."""
     import multiprocessing as mp
     from oracle import letkf_oracle as orc
+    global _ORACLE
     pts = synth.sample_points(wl.nx, wl.ny, wl.nx * wl.ny, seed=3)
-    an = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L, wl.infl)
-    done1, dt1 = _oracle_worker((an, pts, wl.nx, seconds))
+    _ORACLE = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
+                           wl.infl)
+    print(f"cpu baseline: oracle on 1 core for {seconds:.0f} s", file=sys.stderr, flush=True)
+    done1, dt1 = _oracle_worker((pts, wl.nx, seconds))
     cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
     chunks = [pts[i::cores] for i in range(cores)]
+    print(f"cpu baseline: oracle on {cores} processes for {seconds:.0f} s", file=sys.stderr,
+          flush=True)
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(an, c, wl.nx, seconds) for c in chunks])
+        res = pool.map(_oracle_worker, [(c, wl.nx, seconds) for c in chunks])
+    _ORACLE = None
     done_n = sum(r[0] for r in res)
     rate_n = sum(r[0] / r[1] for r in res)
     return {"value": rate_n, "unit": "grid-point analyses/s", "cores": cores, "kind": "oracle",
@@ -376,6 +390,9 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     print(f"generating {wl.name}", file=sys.stderr, flush=True)
     p = synth.make_problem(wl)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, p, args.cpu_seconds, args.cpu_cores)
     xb = torch.from_numpy(p.xb).to(dev)
     obs = dev_obs(torch, p, dev)
     if args.copy_calibration_mib > 0:
@@ -398,6 +415,8 @@ def main():
              "phases_ms": {k: round(v, 4) for k, v in ph.items()},
              "kernels": kernel_roofline(wl, name, ph, launches)}
         if args.error_points > 0:
+            print(f"errors of the {name} form at {args.error_points} sample points",
+                  file=sys.stderr, flush=True)
             r["errors_vs_oracle"] = oracle_errors(wl, p, xa, args.error_points, seed=11)
         del xa
         res[name] = r
@@ -444,6 +463,7 @@ def main():
     del xb, obs
     torch.cuda.empty_cache()
     if args.secondary_steps > 0:
+        print("timing the 256 x 256, k = 32 FP64 workload", file=sys.stderr, flush=True)
         w2 = synth.WORKLOADS["grid256_k32"]
         p2 = synth.make_problem(w2)
         xb2 = torch.from_numpy(p2.xb).to(dev)
@@ -455,6 +475,7 @@ def main():
         del xb2, xa2
         torch.cuda.empty_cache()
     if args.eigh_reps > 0:
+        print("batched eigensolve at the Table I shapes", file=sys.stderr, flush=True)
         out["eigh_table1"] = eigh_table1(L, torch, reps=args.eigh_reps)
     if args.serving_requests > 0:
         from paper_2308_03310_amd import serving
@@ -483,8 +504,8 @@ def main():
                                              tuple(int(g) for g in args.batching_grids.split(",")),
                                              args.batching_precision, args.batching_reps,
                                              args.batching_tune)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, p, args.cpu_seconds, args.cpu_cores)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
