@@ -320,7 +320,7 @@ def cpu_baseline(wl, p, seconds: float, max_cores: int):
     import multiprocessing as mp
     from oracle import letkf_oracle as orc
     global _ORACLE
-    pts = synth.sample_points(wl.nx, wl.ny, wl.nx * wl.ny, seed=3)
+    pts = synth.sample_points(wl.nx, wl.ny, min(wl.nx * wl.ny, 200000), seed=3)
     _ORACLE = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
                            wl.infl)
     print(f"cpu baseline: oracle on 1 core for {seconds:.0f} s", file=sys.stderr, flush=True)

@@ -248,10 +248,12 @@ def sample_points(nx: int, ny: int, n: int, seed: int = 12345) -> np.ndarray:
     fixed = [0, nx - 1, (ny - 1) * nx, ny * nx - 1, (ny // 2) * nx, (ny // 2) * nx + nx - 1, nx // 2,
              (ny - 1) * nx + nx // 2]
     pts = list(dict.fromkeys(p for p in fixed if 0 <= p < nx * ny))
+    seen = set(pts)
     extra = rng.choice(nx * ny, size=min(n, nx * ny), replace=False)
     for p in extra:
         if len(pts) >= n + len(fixed):
             break
-        if p not in pts:
+        if int(p) not in seen:
+            seen.add(int(p))
             pts.append(int(p))
     return np.array(sorted(pts), dtype=np.int64)
