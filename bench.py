@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_GRAM_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 FORMS = (("fp64", 0), ("fp32", 1), ("bf16", 2))
 KERNEL_NAMES = {"gram": {"fp64": "k_gram_f64", "fp32": "k_gram_lp", "bf16": "k_gram_lp"},
-                "evd_update": "k_evd"}
+                "evd_update": "k_evd_xf"}
 # Batched EVD of 16,384 matrices from the LBM-LETKF model on one A100 (FP32,
 # the paper's Table I, EigenG column): context for the eigensolve record.
 PAPER_TABLE1_EIGENG_MS = {16: 1.3, 32: 2.4, 48: 7.8, 64: 14.2}

@@ -303,10 +303,20 @@ hipError_t launch_gram(const BatchMap& bm, int kp, int prec, bool persistent, hi
                                  : launch_gram_lp(bm, kp, prec, persistent, s);
 }
 
+// Standalone batched eigensolve (eigenvalues and eigenvectors).
 hipError_t launch_evd(const BatchMap& bm, int kp, hipStream_t s) {
   if (kp == 16) return launch_evd_kp<16>(bm, s);
   if (kp == 32) return launch_evd_kp<32>(bm, s);
   if (kp == 64) return launch_evd_kp<64>(bm, s);
+  return hipErrorInvalidValue;
+}
+
+// Eigensolve + transform + update of an analysis (the eigenvectors are never
+// formed).
+hipError_t launch_xf(const BatchMap& bm, int kp, hipStream_t s) {
+  if (kp == 16) return launch_evd_xf_kp<16>(bm, s);
+  if (kp == 32) return launch_evd_xf_kp<32>(bm, s);
+  if (kp == 64) return launch_evd_xf_kp<64>(bm, s);
   return hipErrorInvalidValue;
 }
 
@@ -348,7 +358,7 @@ int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* 
     bm.n = std::min(slab, total - g0);
     if (launch_gram(bm, kp, prec, pl->gram_persistent, s) != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
-    if (launch_evd(bm, kp, s) != hipSuccess) return LETKF_EDEVICE;
+    if (launch_xf(bm, kp, s) != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
   }
   return LETKF_OK;

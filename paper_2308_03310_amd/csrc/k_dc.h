@@ -298,42 +298,42 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
   return org;
 }
 
-// One merge level S for every block of the matrix at once.  Lane jj (row jj
-// of T) is position t = jj % S of block a = jj - t.  qs[0..S/2) holds, on
-// entry, row jj of the child's eigenvector matrix restricted to the child's
-// columns; on exit it holds row jj of the merged block's eigenvector matrix
-// restricted to the block's columns (qs[0..S)); lam is the eigenvalue of
-// column jj of the child on entry, of the merged block on exit.  W is this
-// matrix's LDS scratch for the merge matrices (KP * (KP + 1) doubles).
+// What a merge of two children leaves to the construction of its
+// eigenvectors (per lane; block-uniform fields marked).
+struct MergeRoots {
+  double D;        // this lane's pole (child eigenvalue, sign-flipped when beta < 0)
+  bool flip;       // beta < 0: the rank-one update was solved for -T (block-uniform)
+  bool trivial;    // beta z z^T = 0: the block stays decoupled (block-uniform)
+  int K;           // non-deflated poles (block-uniform)
+};
+
+// The eigenvalue problem of one merge level S for every block of the matrix
+// at once: lane jj (column jj of the children's eigenvector matrix, position
+// t = jj % S of block a = jj - t) holds the children's eigenvalue lam and the
+// entry z of the merge vector at its column (the left child's last row, the
+// right child's first row); beta = e_{m-1} is the torn coupling.  Sorts the
+// poles, deflates, solves the secular equation (one root per lane) and
+// recomputes the weights (Loewner); on return L holds, per block: the sorted
+// poles ds and their original positions pm, the deflation map inv, the
+// rotations rot/rc/rs, the non-deflated pairs dw with their rows rw, the
+// roots (rd, rt) and the recomputed weights zh.
 template <int KP, int S>
-__device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP>& L,
-                                         double ej, double* W, int jj, double deps,
-                                         bool& ok) {
-  constexpr int H = S / 2;
-  constexpr int WS = S + 1;                  // row stride of a block's merge matrix
+__device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double beta,
+                                                  DcLds<KP>& L, int jj, double deps, bool& ok) {
   const int t = jj & (S - 1);
   const int a = jj - t;
-  const int m = a + H;
   const int sh0 = (lane_id() & ~(S - 1));    // first lane of this block in the wavefront
-  double* Wb = W + (a / S) * S * WS;         // this block's merge matrix
-  // z: last row of the left child, first row of the right child
-  if (jj == m - 1) {
-#pragma unroll
-    for (int q = 0; q < H; ++q) L.zb[a + q] = qs[q];
-  }
-  if (jj == m) {
-#pragma unroll
-    for (int q = 0; q < H; ++q) L.zb[m + q] = qs[q];
-  }
-  const double beta = __shfl(ej, m - 1, KP);   // e_{m-1}, held by lane m - 1
+  MergeRoots mr;
   const bool flip = beta < 0.0;
   const double D = flip ? -lam : lam;
+  mr.D = D;
+  mr.flip = flip;
   L.dt[jj] = D;
   wave_lds_sync();
-  const double z = L.zb[jj];
   const double nz2 = group_sum<S>(z * z);
   const double rho = fabs(beta) * nz2;
   const bool trivial = !(rho > 0.0);               // uniform per block
+  mr.trivial = trivial;
   const double w = trivial ? 0.0 : z / sqrt(nz2);
   // sort the poles (ties by index)
   int rank = 0;
@@ -408,6 +408,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
   const bool keep = !trivial && L.inv[a + t] >= 0;
   const uint64_t kmask = (__ballot(keep) >> sh0) & (S == 64 ? ~0ull : ((1ull << S) - 1ull));
   const int K = __popcll(kmask);
+  mr.K = K;
   const int kidx = __popcll(kmask & ((1ull << t) - 1ull));
   if (keep) {
     L.inv[a + t] = kidx;
@@ -444,6 +445,42 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
   }
   if (t >= K) L.zh[a + t] = 0.0;
   wave_lds_sync();
+  return mr;
+}
+
+// One merge level S for every block of the matrix at once.  Lane jj (row jj
+// of T) is position t = jj % S of block a = jj - t.  qs[0..S/2) holds, on
+// entry, row jj of the child's eigenvector matrix restricted to the child's
+// columns; on exit it holds row jj of the merged block's eigenvector matrix
+// restricted to the block's columns (qs[0..S)); lam is the eigenvalue of
+// column jj of the child on entry, of the merged block on exit.  W is this
+// matrix's LDS scratch for the merge matrices (KP * (KP + 1) doubles).
+template <int KP, int S>
+__device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP>& L,
+                                         double ej, double* W, int jj, double deps,
+                                         bool& ok) {
+  constexpr int H = S / 2;
+  constexpr int WS = S + 1;                  // row stride of a block's merge matrix
+  const int t = jj & (S - 1);
+  const int a = jj - t;
+  const int m = a + H;
+  double* Wb = W + (a / S) * S * WS;         // this block's merge matrix
+  // z: last row of the left child, first row of the right child
+  if (jj == m - 1) {
+#pragma unroll
+    for (int q = 0; q < H; ++q) L.zb[a + q] = qs[q];
+  }
+  if (jj == m) {
+#pragma unroll
+    for (int q = 0; q < H; ++q) L.zb[m + q] = qs[q];
+  }
+  const double beta = __shfl(ej, m - 1, KP);   // e_{m-1}, held by lane m - 1
+  wave_lds_sync();
+  const double z = L.zb[jj];
+  const MergeRoots mr = merge_roots<KP, S>(z, lam, beta, L, jj, deps, ok);
+  const bool trivial = mr.trivial, flip = mr.flip;
+  const double D = mr.D;
+  const int K = mr.K;
   // column t of the merge matrix (sorted eigenvalue order; rows block-local),
   // left unnormalized: its scale cs goes to the padding column of row t and
   // is applied to the merged rows below (the rotations commute with it)

@@ -79,6 +79,21 @@ __device__ __forceinline__ double group_read_c(double x) {
   }
 }
 
+// Marks the n values of x (n a multiple of 8) as redefined at this point, so
+// that the arithmetic producing them cannot be moved below it.  Instruction
+// selection otherwise places side-effect-free arithmetic anywhere in a long
+// straight-line region (the unrolled Householder steps are one basic block),
+// and sinking a step's updates or selects towards their last use keeps one
+// copy per step live.
+template <int N>
+__device__ __forceinline__ void pin_regs(double* x) {
+  static_assert(N % 8 == 0, "pin_regs: multiple of 8");
+#pragma unroll
+  for (int c = 0; c < N; c += 8)
+    asm volatile("" : "+v"(x[c]), "+v"(x[c + 1]), "+v"(x[c + 2]), "+v"(x[c + 3]), "+v"(x[c + 4]),
+                 "+v"(x[c + 5]), "+v"(x[c + 6]), "+v"(x[c + 7]));
+}
+
 // An integer the compiler cannot see through: LDS addresses derived from it
 // are recomputed after each use point instead of being hoisted out of the
 // unrolled loops (where every one of them would hold a VGPR).
@@ -244,9 +259,10 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // Step i of the reduction (a compile-time index so that a[] stays in
 // registers at every size); alpha = A[i+1][i] and sig = sum_{j>i+1} A[j][i]^2
 // come in from the step before and go out for the step after.
-template <int KP, int i>
-__device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
-                                             double& alpha, double& sig, double& ej) {
+template <int KP, int i, class Sh>
+__device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, int jj,
+                                             double& alpha, double& sig, double& ej,
+                                             double* taus) {
   const int so = opaque(seg * KP);
   double* vb = &sh.vb[0][0] + so;
   double* pb = &sh.wb[0][0] + so;
@@ -258,6 +274,7 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   const double inv = refl ? frcp(alpha - beta) : 0.0;
   const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
   vb[jj] = vj;
+  if (taus != nullptr && jj == 0) taus[i] = tau;
   wave_lds_sync();
   constexpr int c0 = (i + 1) & ~1;
   constexpr bool more = i + 1 < KP - 2;                     // a step follows
@@ -311,25 +328,30 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], EvdLds<KP>& sh, in
   wave_lds_sync();
   if (jj > i) a[i] = vj;
   if (jj == i) ej = beta;
+  // the row and the coupling are final for this step (see pin_regs)
+  pin_regs<KP>(a);
+  asm volatile("" : "+v"(ej));
 }
 
-template <int KP, int... Is>
-__device__ __forceinline__ void tridiag_steps(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
-                                              double& ej,
+template <int KP, class Sh, int... Is>
+__device__ __forceinline__ void tridiag_steps(double (&a)[KP], Sh& sh, int seg, int jj,
+                                              double& ej, double* taus,
                                               std::integer_sequence<int, Is...>) {
   double alpha = group_read_c<KP, 1>(a[0]);
   double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
-  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig, ej), ...);
+  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig, ej, taus), ...);
 }
 
 // The reduction; lane jj ends with dj = T[jj][jj] and ej = T[jj+1][jj]
 // (e_{KP-1} = 0).  The reflectors' tau values are not kept: the
 // back-transformation recovers each from its vector (tau = 2 / v^T v).
-template <int KP>
-__device__ __forceinline__ void tridiagonalize(double (&a)[KP], EvdLds<KP>& sh, int seg, int jj,
-                                               double& dj, double& ej) {
+// taus (nullable): this matrix's KP - 2 reflector tau values, written to LDS
+// by its first lane.
+template <int KP, class Sh>
+__device__ __forceinline__ void tridiagonalize(double (&a)[KP], Sh& sh, int seg, int jj,
+                                               double& dj, double& ej, double* taus = nullptr) {
   ej = 0.0;
-  tridiag_steps<KP>(a, sh, seg, jj, ej, std::make_integer_sequence<int, KP - 2>{});
+  tridiag_steps<KP>(a, sh, seg, jj, ej, taus, std::make_integer_sequence<int, KP - 2>{});
   double dg = 0.0;
 #pragma unroll
   for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;

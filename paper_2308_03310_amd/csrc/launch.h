@@ -154,6 +154,8 @@ hipError_t launch_gram_f64(const BatchMap& bm, int kp, bool persistent, hipStrea
 hipError_t launch_gram_lp(const BatchMap& bm, int kp, int prec, bool persistent, hipStream_t s);
 template <int KP>
 hipError_t launch_evd_kp(const BatchMap& bm, hipStream_t s);
+template <int KP>
+hipError_t launch_evd_xf_kp(const BatchMap& bm, hipStream_t s);
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
                       int force_kx, hipStream_t s);
 
