@@ -188,6 +188,17 @@ typedef struct letkf_cycle_io {
 int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream);
 
 /*
+ * letkf_advance -- the forecast step of the DA cycle (Sec. II-B, step 2)
+ * alone: each io's ensemble (io.xb == io.xa, device) is advanced n_steps
+ * lattice-BGK steps in place, as letkf_cycle does before its analysis; the
+ * observation fields of io are ignored.  Needs a plan made with
+ * LETKF_FLAG_CYCLE (for n_steps > 0).  Asynchronous on hip_stream.  Returns
+ * LETKF_EINVAL for a bad problem index, xa != xb, n_steps < 0 or tau <= 0.5,
+ * LETKF_EBUSY, LETKF_EDEVICE.
+ */
+int letkf_advance(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream);
+
+/*
  * letkf_tune -- project autotuner for the plan's launch settings.  Runs the
  * analyses io[0..n_io) (every problem once gives the batched form) with each
  * candidate setting -- observation-cell edge 4, 8 or 16 lattice points (the

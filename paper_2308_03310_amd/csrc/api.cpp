@@ -622,6 +622,41 @@ bool save_tune_cache(const letkf_plan_s* pl, int cell, int persistent, double ms
 
 }  // namespace
 
+namespace {
+
+// n_steps lattice-BGK steps of the ensemble xb in place, ping-ponging with the
+// problem's BGK buffer so that the last step writes xb (an odd count starts
+// from a copy in the buffer).
+int advance_ensemble(ProblemWs& w, const letkf_cycle_io& c, hipStream_t s) {
+  double* xb = const_cast<double*>(c.io.xb);
+  double* cur = xb;
+  double* nxt = w.bgk;
+  if (c.n_steps % 2 == 1) {
+    const size_t bytes = (size_t)w.npts * 9 * w.p.k * sizeof(double);
+    if (hipMemcpyAsync(w.bgk, xb, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return LETKF_EDEVICE;
+    std::swap(cur, nxt);
+  }
+  for (int st = 0; st < c.n_steps; ++st) {
+    if (launch_bgk(cur, nxt, w.p.k, w.p.nx, w.p.ny, c.tau, c.force_amp, c.force_kx, s) !=
+        hipSuccess)
+      return LETKF_EDEVICE;
+    std::swap(cur, nxt);
+  }
+  return LETKF_OK;
+}
+
+int check_cycle_io(const letkf_plan_s* plan, const letkf_cycle_io& c) {
+  const int rc = check_io(plan, c.io);
+  if (rc != LETKF_OK) return rc;
+  if (c.io.xa != c.io.xb || c.n_steps < 0) return LETKF_EINVAL;
+  if (!(c.tau > 0.5) || !std::isfinite(c.tau) || !std::isfinite(c.force_amp)) return LETKF_EINVAL;
+  if (c.n_steps > 0 && !plan->probs[c.io.problem].bgk) return LETKF_EINVAL;
+  return LETKF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* letkf_strerror(int code) {
@@ -790,12 +825,8 @@ int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip
 int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream) {
   if (!plan || (!io && n_io > 0) || n_io < 0) return LETKF_EINVAL;
   for (int i = 0; i < n_io; ++i) {
-    const int rc = check_io(plan, io[i].io);
+    const int rc = check_cycle_io(plan, io[i]);
     if (rc != LETKF_OK) return rc;
-    if (io[i].io.xa != io[i].io.xb || io[i].n_steps < 0) return LETKF_EINVAL;
-    if (!(io[i].tau > 0.5) || !std::isfinite(io[i].tau) || !std::isfinite(io[i].force_amp))
-      return LETKF_EINVAL;
-    if (io[i].n_steps > 0 && !plan->probs[io[i].io.problem].bgk) return LETKF_EINVAL;
   }
   std::vector<letkf_io> ios(n_io);
   for (int i = 0; i < n_io; ++i) ios[i] = io[i].io;
@@ -806,33 +837,35 @@ int letkf_cycle(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void*
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::vector<letkf_io> dio;
   int rc = device_ios(plan, ios.data(), n_io, s, dio);
+  // the advanced state is in io.xb whether or not the analysis runs
   std::vector<const double*> src(n_io);
   for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
-    const letkf_cycle_io& c = io[i];
-    ProblemWs& w = plan->probs[c.io.problem];
-    // Ping-pong between the caller's ensemble and the plan's buffer, arranged
-    // so that the last step writes the caller's ensemble (an odd count starts
-    // from a copy in the buffer): the advanced state is in io.xb whether or
-    // not the analysis runs.
-    double* xb = const_cast<double*>(c.io.xb);
-    double* cur = xb;
-    double* nxt = w.bgk;
-    if (c.n_steps % 2 == 1) {
-      const size_t bytes = (size_t)w.npts * 9 * w.p.k * sizeof(double);
-      if (hipMemcpyAsync(w.bgk, xb, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        rc = LETKF_EDEVICE;
-      std::swap(cur, nxt);
-    }
-    for (int st = 0; st < c.n_steps && rc == LETKF_OK; ++st) {
-      if (launch_bgk(cur, nxt, w.p.k, w.p.nx, w.p.ny, c.tau, c.force_amp, c.force_kx, s) !=
-          hipSuccess)
-        rc = LETKF_EDEVICE;
-      std::swap(cur, nxt);
-    }
-    src[i] = xb;
+    rc = advance_ensemble(plan->probs[io[i].io.problem], io[i], s);
+    src[i] = io[i].io.xb;
   }
   if (rc == LETKF_OK)
     rc = enqueue(plan, dio.data(), src.data(), n_io, covers_all_once(plan, ios.data(), n_io), s);
+  plan->last_stream = s;
+  plan->busy.store(0);
+  return rc;
+}
+
+int letkf_advance(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, void* hip_stream) {
+  if (!plan || (!io && n_io > 0) || n_io < 0) return LETKF_EINVAL;
+  for (int i = 0; i < n_io; ++i) {
+    if (io[i].io.problem < 0 || io[i].io.problem >= (int)plan->probs.size()) return LETKF_EINVAL;
+    if (!io[i].io.xb || io[i].io.xa != io[i].io.xb || io[i].n_steps < 0) return LETKF_EINVAL;
+    if (!(io[i].tau > 0.5) || !std::isfinite(io[i].tau) || !std::isfinite(io[i].force_amp))
+      return LETKF_EINVAL;
+    if (io[i].n_steps > 0 && !plan->probs[io[i].io.problem].bgk) return LETKF_EINVAL;
+  }
+  int expect = 0;
+  if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int rc = LETKF_OK;
+  for (int i = 0; i < n_io && rc == LETKF_OK; ++i)
+    rc = advance_ensemble(plan->probs[io[i].io.problem], io[i], s);
   plan->last_stream = s;
   plan->busy.store(0);
   return rc;

@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.letkf_analyze.restype = ctypes.c_int
     lib.letkf_cycle.argtypes = [vp, ctypes.POINTER(letkf_cycle_io), i32, vp]
     lib.letkf_cycle.restype = ctypes.c_int
+    lib.letkf_advance.argtypes = [vp, ctypes.POINTER(letkf_cycle_io), i32, vp]
+    lib.letkf_advance.restype = ctypes.c_int
     lib.letkf_status.argtypes = [vp, i32]
     lib.letkf_status.restype = ctypes.c_int
     lib.letkf_plan_destroy.argtypes = [vp]
@@ -208,13 +210,16 @@ def _validate(plan: int, io: letkf_io) -> None:
     probs, flags = entry
     if not 0 <= io.problem < len(probs):
         raise ValueError(f"problem index {io.problem} out of range ({len(probs)} problems)")
-    p = probs[io.problem]
+    _validate_sizes(probs[io.problem], io, flags)
+
+
+def _validate_sizes(p: letkf_problem, io: letkf_io, flags: int) -> None:
     counts = getattr(io, "_numel", None)
     if counts is None:
         raise ValueError("letkf_io must be made with make_io (its array sizes are checked)")
     state = p.nx * p.ny * 9 * p.k
     if counts[0] != state or counts[1] != state:
-        raise ValueError(f"xb / xa hold {counts[0]} / {counts[1]} values, problem {io.problem} "
+        raise ValueError(f"xb / xa hold {counts[0]} / {counts[1]} values, the problem "
                          f"needs {state} ([{p.k}][9][{p.ny}][{p.nx}])")
     if any(c != io.n_obs for c in counts[2:]):
         raise ValueError(f"observation arrays differ in length: {counts[2:]}")
@@ -251,6 +256,25 @@ def letkf_cycle(plan: int, ios: Iterable[letkf_cycle_io], stream=None) -> int:
         _validate(plan, getattr(c, "_io", c.io))
     arr = (letkf_cycle_io * len(ios))(*ios)
     return _check(load_library().letkf_cycle(plan, arr, len(ios), _stream(stream)), "letkf_cycle")
+
+
+def letkf_advance(plan: int, ios: Iterable[letkf_cycle_io], stream=None) -> int:
+    """The forecast step alone: each ensemble advanced n_steps BGK steps in place."""
+    ios = list(ios)
+    for c in ios:
+        io = getattr(c, "_io", c.io)
+        entry = _plans.get(plan)
+        if entry is not None:
+            probs, _ = entry
+            if not 0 <= io.problem < len(probs):
+                raise ValueError(f"problem index {io.problem} out of range")
+            p = probs[io.problem]
+            counts = getattr(io, "_numel", None)
+            if counts is None or counts[0] != p.nx * p.ny * 9 * p.k:
+                raise ValueError("advance: the ensemble does not fit the problem")
+    arr = (letkf_cycle_io * len(ios))(*ios)
+    return _check(load_library().letkf_advance(plan, arr, len(ios), _stream(stream)),
+                  "letkf_advance")
 
 
 def letkf_status(plan: int, sync: bool = True) -> int:
