@@ -288,6 +288,34 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
 int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, double* vec,
                        int32_t* status, void* hip_stream);
 
+/*
+ * letkf_analyze_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one analysis of one problem, as letkf_analyze on a plan made
+ * for *prob alone with no flags, without a plan.  Its workspace (the
+ * point-major ensemble, the sorted observations and their perturbations, the
+ * cell table, the Gram output slab) is a static device array of
+ * LETKF_NOALLOC_BYTES per GPU, held from the library's first use of the GPU
+ * until the process ends; the call allocates nothing.
+ *   prob: the problem (as for letkf_plan; precision any form);
+ *   io:   its arrays, device memory (io->problem is ignored; xa may equal xb);
+ *   status: device int32, caller-owned: set to 0 on the stream, then the
+ *        device status bits of the analysis are OR-ed in (bit n <-> code n:
+ *        LETKF_EINVAL for an invalid observation, LETKF_ENONFINITE,
+ *        LETKF_ENOTCONV); read it after the stream has executed the call.
+ * Asynchronous on hip_stream.  Returns LETKF_EINVAL as letkf_plan and
+ * letkf_analyze's host checks do, LETKF_ENOMEM when the problem's workspace
+ * (about 9 k nx ny doubles for the ensemble plus n_obs_max (KP + 6) doubles,
+ * with KP = max(16, the power of two >= k), plus a Gram slab of at least 256
+ * points) does not fit in LETKF_NOALLOC_BYTES, LETKF_EDEVICE without a gfx950
+ * device.  All calls on one GPU share its array: calls whose executions
+ * overlap on one GPU (different streams, or host threads) race and give
+ * undefined results; calls ordered on one stream are safe.
+ */
+#define LETKF_NOALLOC_BYTES (64ull << 20)
+int letkf_analyze_noalloc(const letkf_problem* prob, const letkf_io* io, int32_t* status,
+                          void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -657,13 +658,64 @@ int check_cycle_io(const letkf_plan_s* plan, const letkf_cycle_io& c) {
 
 }  // namespace
 
+namespace {
+
+// Workspace of letkf_analyze_noalloc: a file-scope device array, one copy per
+// GPU (made when the code object is loaded there, held until the process
+// ends).  Host code never passes the array's name to a kernel: the address of
+// each device's copy comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is used.
+constexpr uint64_t kNoAllocBytes = LETKF_NOALLOC_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+int noalloc_base(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return LETKF_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+      return LETKF_EDEVICE;
+    g_noalloc_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return LETKF_OK;
+}
+
+// Consecutive 256-byte-aligned pieces of the static workspace; null once it
+// is exhausted (nothing is written while the layout is computed).
+struct Carve {
+  unsigned char* base;
+  uint64_t off = 0;
+  bool ok = true;
+  template <class T>
+  T* take(uint64_t count) {
+    off = (off + 255) & ~255ull;
+    const uint64_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 256;
+    if (!ok || off + bytes > kNoAllocBytes) {
+      ok = false;
+      return nullptr;
+    }
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char* letkf_strerror(int code) {
   switch (code) {
     case LETKF_OK: return "ok";
     case LETKF_EINVAL: return "invalid argument";
-    case LETKF_ENOMEM: return "out of device memory or over the HBM budget";
+    case LETKF_ENOMEM:
+      return "out of device memory, over the HBM budget, or larger than the no-allocation "
+             "workspace";
     case LETKF_EDEVICE: return "no usable gfx950 device or HIP runtime error";
     case LETKF_EBUSY: return "plan in use by another call";
     case LETKF_ENONFINITE: return "non-finite analysis value";
@@ -1067,6 +1119,79 @@ int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, d
   const int kp = pow2_at_least16(k);
   return launch_evd(bm, kp, static_cast<hipStream_t>(hip_stream)) == hipSuccess ? LETKF_OK
                                                                                  : LETKF_EDEVICE;
+}
+
+int letkf_analyze_noalloc(const letkf_problem* prob, const letkf_io* io, int32_t* status,
+                          void* hip_stream) {
+  if (!prob || !io || !status) return LETKF_EINVAL;
+  int rc = check_problem(*prob);
+  if (rc != LETKF_OK) return rc;
+  if (io->n_obs < 0 || io->n_obs > prob->n_obs_max || !io->xb || !io->xa) return LETKF_EINVAL;
+  if (io->n_obs > 0 &&
+      (!io->obs_ix || !io->obs_iy || !io->obs_kind || !io->obs_val || !io->obs_var))
+    return LETKF_EINVAL;
+  int dev = 0;
+  rc = check_device(&dev);
+  if (rc != LETKF_OK) return rc;
+  Carve cv;
+  rc = noalloc_base(dev, &cv.base);
+  if (rc != LETKF_OK) return rc;
+  // layout of one problem's workspace (as letkf_plan's, without the tuner's
+  // extra cells, the BGK buffer or host-observation copies)
+  ProblemWs w;
+  std::memset(&w, 0, sizeof(ProblemWs));
+  w.p = *prob;
+  plan_sizes(w);
+  const uint64_t no = (uint64_t)w.nobs_alloc;
+  w.abort_flag = cv.take<int>(1);
+  w.xt = cv.take<double>((uint64_t)w.npts * 9 * w.p.k);
+  w.obs_cell = cv.take<int>(no);
+  w.perm = cv.take<int>(no);
+  w.ox = cv.take<int>(no);
+  w.oy = cv.take<int>(no);
+  if (w.p.precision == LETKF_PREC_FP64)
+    w.Yb = cv.take<double>(no * w.kp);
+  else
+    w.Ylp = cv.take<unsigned char>(no * w.kp * (w.p.precision == LETKF_PREC_FP32 ? 4 : 2));
+  w.d = cv.take<double>(no);
+  w.rinv = cv.take<double>(no);
+  w.cell_count = cv.take<int>(w.ncells);
+  w.cell_start = cv.take<int>((uint64_t)w.ncells + 1);
+  w.cell_fill = cv.take<int>(w.ncells);
+  // the Gram output slab takes what is left, at least 256 points (or all)
+  const uint64_t per_pt = ((uint64_t)w.nb * 256 + w.kp) * sizeof(double);
+  const uint64_t left = cv.ok && cv.off + 1024 < kNoAllocBytes ? kNoAllocBytes - cv.off - 1024 : 0;
+  const int slab = (int)std::min<uint64_t>((uint64_t)w.npts, left / per_pt);
+  if (!cv.ok || slab < std::min(256, w.npts)) return LETKF_ENOMEM;
+  double* slab_C = cv.take<double>((uint64_t)slab * w.nb * 256);
+  double* slab_b = cv.take<double>((uint64_t)slab * w.kp);
+  if (!cv.ok) return LETKF_ENOMEM;
+
+  DeviceGuard guard(dev);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // status and abort flag start at zero (fill kernels: no memset nodes under capture)
+  if (launch_fill_i32(status, 1, 0, s) != hipSuccess) return LETKF_EDEVICE;
+  if (launch_fill_i32(w.abort_flag, 1, 0, s) != hipSuccess) return LETKF_EDEVICE;
+  const ObsArgs oa = obs_args(w, *io, status);
+  if (launch_bin(oa, s) != hipSuccess) return LETKF_EDEVICE;
+  if (launch_transpose_in(io->xb, w.xt, w.p.k, w.npts, w.abort_flag, s) != hipSuccess)
+    return LETKF_EDEVICE;
+  if (launch_obs_operator(oa, s) != hipSuccess) return LETKF_EDEVICE;
+  BatchMap bm{};
+  bm.nprob = 1;
+  bm.C = slab_C;
+  bm.b = slab_b;
+  bm.g_inline = gram_desc(w);
+  bm.e_inline = evd_desc(w, status);
+  for (int g0 = 0; g0 < w.npts; g0 += slab) {
+    bm.g0 = g0;
+    bm.n = std::min(slab, w.npts - g0);
+    if (launch_gram(bm, w.kp, w.p.precision, false, s) != hipSuccess) return LETKF_EDEVICE;
+    if (launch_xf(bm, w.kp, s) != hipSuccess) return LETKF_EDEVICE;
+  }
+  if (launch_transpose_out(w.xt, io->xa, w.p.k, w.npts, w.abort_flag, s) != hipSuccess)
+    return LETKF_EDEVICE;
+  return LETKF_OK;
 }
 
 }  // extern "C"

@@ -101,6 +101,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.letkf_phase_times.restype = ctypes.c_int
     lib.letkf_eigh_batched.argtypes = [dp, i32, i32, dp, dp, dp, vp]
     lib.letkf_eigh_batched.restype = ctypes.c_int
+    lib.letkf_analyze_noalloc.argtypes = [ctypes.POINTER(letkf_problem), ctypes.POINTER(letkf_io),
+                                          dp, vp]
+    lib.letkf_analyze_noalloc.restype = ctypes.c_int
     lib.letkf_tune.argtypes = [vp, ctypes.POINTER(letkf_io), i32, vp, ctypes.POINTER(letkf_tuning)]
     lib.letkf_tune.restype = ctypes.c_int
     lib.letkf_set_tuning.argtypes = [vp, ctypes.POINTER(letkf_tuning)]
@@ -314,6 +317,19 @@ def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
         _ptr(a, torch.float64), batch, k, _ptr(lam, torch.float64), _ptr(vec, torch.float64),
         _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
         "letkf_eigh_batched")
+
+
+def letkf_analyze_noalloc(problem: letkf_problem, io: letkf_io, status, stream=None) -> int:
+    """One analysis of one problem without a plan (the library's static
+    workspace; nothing is allocated).  status: a device int32 tensor that
+    receives the analysis' device status bits."""
+    import torch
+    _validate_sizes(problem, io, 0)
+    if status is None or status.numel() < 1:
+        raise ValueError("analyze_noalloc: status needs one int32")
+    return _check(load_library().letkf_analyze_noalloc(
+        ctypes.byref(problem), ctypes.byref(io), _ptr(status, torch.int32), _stream(stream)),
+        "letkf_analyze_noalloc")
 
 
 def letkf_tune(plan: int, ios: Iterable[letkf_io], stream=None) -> dict:

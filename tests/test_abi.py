@@ -117,6 +117,26 @@ def test_null_handles(lib):
     assert lib.letkf_eigh_batched(None, 4, 70, None, None, None, None) == L.LETKF_EINVAL
     assert lib.letkf_eigh_batched(None, 0, 8, None, None, None, None) == L.LETKF_OK
     assert lib.letkf_eigh_batched(None, 3, 8, None, None, None, None) == L.LETKF_EINVAL
+    assert lib.letkf_analyze_noalloc(None, None, None, None) == L.LETKF_EINVAL
+
+
+def test_noalloc_host_checks(lib):
+    # bad problem, too many observations, missing arrays: refused before the device
+    x = ctypes.c_double(0.0)
+    st = ctypes.c_int32(0)
+    bad = L.make_problem(32, 32, 1, 10, 4.0, 1.1)
+    io = L.letkf_io(0, 0, ctypes.addressof(x), ctypes.addressof(x), 0, 0, 0, 0, 0)
+    assert lib.letkf_analyze_noalloc(ctypes.byref(bad), ctypes.byref(io), ctypes.addressof(st),
+                                     None) == L.LETKF_EINVAL
+    p = L.make_problem(**GOOD)
+    many = L.letkf_io(0, p.n_obs_max + 1, ctypes.addressof(x), ctypes.addressof(x), 0, 0, 0, 0, 0)
+    assert lib.letkf_analyze_noalloc(ctypes.byref(p), ctypes.byref(many), ctypes.addressof(st),
+                                     None) == L.LETKF_EINVAL
+    noarr = L.letkf_io(0, 1, ctypes.addressof(x), ctypes.addressof(x), 0, 0, 0, 0, 0)
+    assert lib.letkf_analyze_noalloc(ctypes.byref(p), ctypes.byref(noarr), ctypes.addressof(st),
+                                     None) == L.LETKF_EINVAL
+    assert lib.letkf_analyze_noalloc(ctypes.byref(p), ctypes.byref(io), None,
+                                     None) == L.LETKF_EINVAL
 
 
 def test_valid_descriptor_without_gpu_is_edevice(lib):
