@@ -259,7 +259,7 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // Step i of the reduction (a compile-time index so that a[] stays in
 // registers at every size); alpha = A[i+1][i] and sig = sum_{j>i+1} A[j][i]^2
 // come in from the step before and go out for the step after.
-template <int KP, int i, class Sh>
+template <int KP, int i, bool STREAM, class Sh>
 __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, int jj,
                                              double& alpha, double& sig, double& ej,
                                              double* taus) {
@@ -278,7 +278,7 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
   wave_lds_sync();
   constexpr int c0 = (i + 1) & ~1;
   constexpr bool more = i + 1 < KP - 2;                     // a step follows
-  if constexpr (KP <= 32) {
+  if constexpr (!STREAM) {
     // the trailing parts of v and p go to registers in one burst of LDS
     // reads each (one wait per vector instead of one per few products)
     double vv[KP], pp[KP];
@@ -333,25 +333,26 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
   asm volatile("" : "+v"(ej));
 }
 
-template <int KP, class Sh, int... Is>
+template <int KP, bool STREAM, class Sh, int... Is>
 __device__ __forceinline__ void tridiag_steps(double (&a)[KP], Sh& sh, int seg, int jj,
                                               double& ej, double* taus,
                                               std::integer_sequence<int, Is...>) {
   double alpha = group_read_c<KP, 1>(a[0]);
   double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
-  (tridiag_step<KP, Is>(a, sh, seg, jj, alpha, sig, ej, taus), ...);
+  (tridiag_step<KP, Is, STREAM>(a, sh, seg, jj, alpha, sig, ej, taus), ...);
 }
 
 // The reduction; lane jj ends with dj = T[jj][jj] and ej = T[jj+1][jj]
 // (e_{KP-1} = 0).  The reflectors' tau values are not kept: the
 // back-transformation recovers each from its vector (tau = 2 / v^T v).
 // taus (nullable): this matrix's KP - 2 reflector tau values, written to LDS
-// by its first lane.
-template <int KP, class Sh>
+// by its first lane.  STREAM: the broadcast vectors come from LDS in chunks
+// (fewer registers) rather than in one burst.
+template <int KP, bool STREAM = (KP > 32), class Sh>
 __device__ __forceinline__ void tridiagonalize(double (&a)[KP], Sh& sh, int seg, int jj,
                                                double& dj, double& ej, double* taus = nullptr) {
   ej = 0.0;
-  tridiag_steps<KP>(a, sh, seg, jj, ej, taus, std::make_integer_sequence<int, KP - 2>{});
+  tridiag_steps<KP, STREAM>(a, sh, seg, jj, ej, taus, std::make_integer_sequence<int, KP - 2>{});
   double dg = 0.0;
 #pragma unroll
   for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;

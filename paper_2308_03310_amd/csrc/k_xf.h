@@ -43,6 +43,21 @@ constexpr int kXfDown = 9;    // vectors on the way down
 constexpr int kXfRec = 14;    // record of a non-deflated pole on the way up: d, zhat, 12 entries
 constexpr int kXfRecB = 12;   // record of a non-deflated root on the way down: dorg, tau, 9 entries
 
+// Register budget of the transform kernel: the Householder vectors stay in
+// the lanes' registers through the divide and conquer only up to this width
+// (beyond it they wait in the point's consumed Gram output), and the
+// reduction streams its broadcast vectors from LDS above this width.
+#ifndef LETKF_XF_REFL_REG_MAX
+#define LETKF_XF_REFL_REG_MAX 32
+#endif
+#ifndef LETKF_XF_BURST_MAX
+#define LETKF_XF_BURST_MAX 32
+#endif
+template <int KP>
+constexpr bool kXfReflInRegisters = KP <= LETKF_XF_REFL_REG_MAX;
+template <int KP>
+constexpr bool kXfStream = KP > LETKF_XF_BURST_MAX;
+
 template <int KP>
 struct XfLds {
   static constexpr int G = 64 / KP;
@@ -246,7 +261,7 @@ __device__ __forceinline__ void xf_reflect_forward(double (&x)[16], const double
 }
 
 // Z H^T = Z H_{n-3} .. H_0: reflectors in descending order, 16 at a time,
-// from the lanes' registers (KP <= LETKF_REFL_REG_MAX) or from the global
+// from the lanes' registers (KP <= LETKF_XF_REFL_REG_MAX) or from the global
 // copy, the next chunk's loads in flight while a chunk is applied.
 template <int KP, int I0>
 __device__ __forceinline__ void xf_reflect_backward_regs(double (&x)[16], const double (&a)[KP],
@@ -580,11 +595,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   double a[KP];
   xf_load_row<KP>(e, jj, pl, valid, a);
   double dj, ej;
-  tridiagonalize<KP>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
+  tridiagonalize<KP, kXfStream<KP>>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
   // the reflectors' global copy (when the registers cannot keep them through
   // the divide and conquer): this point's consumed Gram output
   double* rv = e.C + (size_t)(valid ? pl : 0) * ((KP / 16) * (KP / 16 + 1) / 2) * 256;
-  if constexpr (!kReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
+  if constexpr (!kXfReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
 
   // rows of X: dX (nine components, ensemble mean removed) and b, row-part layout
   const int q = jj >> 4, c = jj & 15;
@@ -644,7 +659,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int v = 0; v < kXfDown; ++v) mic = v == c ? mi[v] : mic;
   wave_lds_sync();
   constexpr int ILAST = ((KP - 3) / 16) * 16;
-  if constexpr (kReflInRegisters<KP>) {
+  if constexpr (kXfReflInRegisters<KP>) {
     xf_reflect_backward_regs<KP, ILAST>(x, a, sh, seg, jj, q);
   } else {
     double nxt[16];
