@@ -106,13 +106,14 @@ def dev_obs(torch, p, dev):
                  (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
 
 
-def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup):
+def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup, flags=0):
     """steps whole analyses of one problem in one precision form on torch's
     current stream, bracketed by synchronizations: returns (analyses/s, ms per
     analysis, per-phase ms per analysis, launches per phase, the analysis)."""
     xa = torch.empty_like(xb)
     plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, int(obs[0].numel()), wl.L, wl.infl,
-                                        precision=precision)], flags=L.LETKF_FLAG_PHASE_TIMING)
+                                        precision=precision)],
+                        flags=L.LETKF_FLAG_PHASE_TIMING | flags)
     try:
         io = [L.make_io(0, xb, xa, obs)]
         stream = torch.cuda.current_stream()
@@ -160,14 +161,13 @@ def kernel_roofline(wl, form, per_call, launches):
     return out
 
 
-def oracle_errors(wl, p, xa, n_points, seed):
-    """Errors of an analysis against the FP64 oracle at seeded sample points:
-    relative L2 of the whole, of the increment, of the analysis mean and of
-    the spread, and the largest error of one point relative to its norm."""
-    from oracle import letkf_oracle as orc
-    pts = synth.sample_points(wl.nx, wl.ny, n_points, seed=seed)
-    ref = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
-                       wl.infl).run(pts)
+def oracle_errors(wl, p, xa, refs):
+    """Errors of an analysis against the FP64 oracle at the seeded sample
+    points whose oracle values the CPU-baseline leg computed (refs = (points,
+    [n, k, 9] values)): relative L2 of the whole, of the increment, of the
+    analysis mean and of the spread, and the largest error of one point
+    relative to its norm."""
+    pts, ref = refs
     iy, ix = pts // wl.nx, pts % wl.nx
     got = np.moveaxis(xa[:, :, iy, ix].cpu().numpy(), -1, 0)        # [n, k, 9]
     xb = np.moveaxis(p.xb[:, :, iy, ix], -1, 0)
@@ -187,42 +187,76 @@ def oracle_errors(wl, p, xa, n_points, seed):
 def eigh_table1(L, torch, batch=16384, ks=(16, 32, 48, 64), reps=10):
     """The standalone batched eigensolve at the shapes of the paper's Table I
     (16,384 matrices per batch): LETKF-form matrices ((k-1)/rho) I + Y^T Y
-    with Y of 2k centred rows."""
+    with Y of 2k centred rows (cond about 1.05); beside it the Newton-Schulz
+    inverse square root (the transform's other route, no EVD) of the same
+    matrices and of a spread family whose Y^T Y is scaled to cond(Q) = 1e3
+    (the step count of the iteration grows with cond, the EVD's does not)."""
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev).manual_seed(7)
     out = {"batch": batch, "unit": "ns per matrix", "precision": "fp64",
            "context": "paper Table I (EigenG, FP32, one A100), ms per 16,384 matrices"}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        if int(st.item()) != 0:
+            raise SystemExit(f"k={k}: not converged")
+        return e0.elapsed_time(e1) / reps
+
     for k in ks:
         Y = torch.randn(batch, 2 * k, k, generator=g, device=dev, dtype=torch.float64)
         Y = Y - Y.mean(dim=2, keepdim=True)
-        A = torch.matmul(Y.transpose(1, 2).contiguous(), Y) * (1.0 / (2 * k)) + \
-            (k - 1) / 1.1 * torch.eye(k, device=dev, dtype=torch.float64)
-        A = A.contiguous()
+        C = torch.matmul(Y.transpose(1, 2).contiguous(), Y) * (1.0 / (2 * k))
+        del Y
+        eye = (k - 1) / 1.1 * torch.eye(k, device=dev, dtype=torch.float64)
         lam = torch.empty(batch, k, dtype=torch.float64, device=dev)
         vec = torch.empty(batch, k, k, dtype=torch.float64, device=dev)
-        st = torch.zeros(1, dtype=torch.int32, device=dev)
-        for _ in range(3):
-            L.letkf_eigh_batched(A, lam, vec, st)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            L.letkf_eigh_batched(A, lam, vec, st)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        if int(st.item()) != 0:
-            raise SystemExit(f"eigh_batched k={k}: not converged")
-        # residual check on a few matrices
+        xs = torch.empty(batch, k, k, dtype=torch.float64, device=dev)
+        nst = torch.empty(batch, dtype=torch.int32, device=dev)
         i = torch.arange(0, batch, batch // 8, device=dev)
-        R = torch.matmul(vec[i] * lam[i][:, None, :], vec[i].transpose(1, 2).contiguous()) - A[i]
-        res = float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(A[i])).max())
-        tf = 9 * k ** 3 * batch / (ms / 1e3) / 1e12
-        out[f"k{k}"] = {"ms": round(ms, 4), "ns_per_matrix": round(ms * 1e6 / batch, 1),
-                        "tflops_9k3": round(tf, 3), "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 4),
-                        "max_rel_residual": res, "paper_a100_fp32_ms": PAPER_TABLE1_EIGENG_MS.get(k)}
-        del Y, A, lam, vec
+        rec = {}
+        for fam in ("table1", "cond1e3"):
+            if fam == "table1":
+                A = (C + eye).contiguous()
+            else:
+                lmax = torch.linalg.eigvalsh(C[:64]).amax(dim=1).mean()
+                A = (C * ((1e3 - 1.0) * (k - 1) / 1.1 / lmax) + eye).contiguous()
+            ms = timed(lambda: L.letkf_eigh_batched(A, lam, vec, st))
+            R = torch.matmul(vec[i] * lam[i][:, None, :], vec[i].transpose(1, 2).contiguous()) - A[i]
+            res = float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(A[i])).max())
+            cond = float((lam[i].amax(dim=1) / lam[i].amin(dim=1)).median())
+            tf = 9 * k ** 3 * batch / (ms / 1e3) / 1e12
+            ms_ns = timed(lambda: L.letkf_invsqrt_batched(A, xs, st, nst))
+            steps = float(nst.double().mean())
+            R = torch.matmul(vec[i] * lam[i].rsqrt()[:, None, :], vec[i].transpose(1, 2).contiguous())
+            dif = float((torch.linalg.matrix_norm(xs[i] - R) / torch.linalg.matrix_norm(R)).max())
+            tf_ns = 6 * k ** 3 * steps * batch / (ms_ns / 1e3) / 1e12
+            r = {"median_cond": round(cond, 3),
+                 "eigh": {"ms": round(ms, 4), "ns_per_matrix": round(ms * 1e6 / batch, 1),
+                          "tflops_9k3": round(tf, 3),
+                          "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 4),
+                          "max_rel_residual": res},
+                 "nsqrt": {"ms": round(ms_ns, 4), "ns_per_matrix": round(ms_ns * 1e6 / batch, 1),
+                           "mean_steps": round(steps, 2), "tflops_6k3_per_step": round(tf_ns, 3),
+                           "frac_fp64_peak": round(tf_ns / PEAK_FP64_TFLOPS, 4),
+                           "speedup_vs_eigh": round(ms / ms_ns, 3),
+                           "max_rel_diff_vs_evd_form": dif}}
+            rec[fam] = r
+            del A
+        # the Table I record keeps its flat keys (the EVD on the Table I form)
+        t1 = rec["table1"]["eigh"]
+        out[f"k{k}"] = dict(t1, paper_a100_fp32_ms=PAPER_TABLE1_EIGENG_MS.get(k),
+                            nsqrt=rec["table1"]["nsqrt"], cond1e3=rec["cond1e3"])
+        del C, lam, vec, xs, nst
     torch.cuda.empty_cache()
     return out
 
@@ -310,19 +344,26 @@ def _oracle_worker(args):
     return done, dt
 
 
-def cpu_baseline(wl, p, seconds: float, max_cores: int):
+def cpu_baseline(wl, p, seconds: float, max_cores: int, error_points: int):
     """The oracle, as it is, on a bounded sample of the workload's grid points:
     one process with one BLAS thread, then one such process per host core
     (forked after the forecast observations are computed, so every process
     evaluates points of the same analysis; the workers inherit it rather than
     receive a copy).  Runs before the GPU is initialised, so the forks carry
-    no device state."""
+    no device state.  Also returns the oracle's values at error_points seeded
+    points (points, [n, k, 9]), the references the GPU forms are checked
+    against; this leg is the only one that runs the oracle."""
     import multiprocessing as mp
     from oracle import letkf_oracle as orc
     global _ORACLE
     pts = synth.sample_points(wl.nx, wl.ny, min(wl.nx * wl.ny, 200000), seed=3)
     _ORACLE = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
                            wl.infl)
+    refs = None
+    if error_points > 0:
+        rp = synth.sample_points(wl.nx, wl.ny, error_points, seed=11)
+        print(f"oracle values at {len(rp)} sample points", file=sys.stderr, flush=True)
+        refs = (rp, _ORACLE.run(rp))
     print(f"cpu baseline: oracle on 1 core for {seconds:.0f} s", file=sys.stderr, flush=True)
     done1, dt1 = _oracle_worker((pts, wl.nx, seconds))
     cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
@@ -335,7 +376,7 @@ def cpu_baseline(wl, p, seconds: float, max_cores: int):
     _ORACLE = None
     done_n = sum(r[0] for r in res)
     rate_n = sum(r[0] / r[1] for r in res)
-    return {"value": rate_n, "unit": "grid-point analyses/s", "cores": cores, "kind": "oracle",
+    return refs, {"value": rate_n, "unit": "grid-point analyses/s", "cores": cores, "kind": "oracle",
             "single_core_value": done1 / dt1,
             "sample": f"seeded random grid points of {wl.name} (forecast observations of all "
                       f"{len(p.obs_ix)} observations computed first): {done1} points in "
@@ -354,12 +395,17 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,bf16",
                     help="precision forms timed (the headline's and fp64 are always included)")
     ap.add_argument("--error-points", type=int, default=24,
-                    help="sample points at which each form is compared with the oracle (0: skip)")
+                    help="sample points at which each form is compared with the oracle (0: "
+                         "skip; the oracle runs in the CPU-baseline leg, which "
+                         "--no-cpu-baseline skips with them)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-cores", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary-steps", type=int, default=10,
                     help="timed steps of the 256^2, k = 32 FP64 workload (0 to skip)")
+    ap.add_argument("--nsqrt-steps", type=int, default=3,
+                    help="analyses timed with the Newton-Schulz route to the transform "
+                         "(LETKF_FLAG_NSQRT, FP64 form) beside the EVD route (0: skip)")
     ap.add_argument("--eigh-reps", type=int, default=10,
                     help="timed batches of the Table I eigensolve shapes (0 to skip)")
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -390,9 +436,9 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     print(f"generating {wl.name}", file=sys.stderr, flush=True)
     p = synth.make_problem(wl)
-    cpu = None
+    cpu = refs = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, p, args.cpu_seconds, args.cpu_cores)
+        refs, cpu = cpu_baseline(wl, p, args.cpu_seconds, args.cpu_cores, args.error_points)
     xb = torch.from_numpy(p.xb).to(dev)
     obs = dev_obs(torch, p, dev)
     if args.copy_calibration_mib > 0:
@@ -414,13 +460,23 @@ def main():
         r = {"value": round(rate, 1), "ms_per_analysis": round(ms, 3),
              "phases_ms": {k: round(v, 4) for k, v in ph.items()},
              "kernels": kernel_roofline(wl, name, ph, launches)}
-        if args.error_points > 0:
-            print(f"errors of the {name} form at {args.error_points} sample points",
-                  file=sys.stderr, flush=True)
-            r["errors_vs_oracle"] = oracle_errors(wl, p, xa, args.error_points, seed=11)
+        if refs is not None:
+            r["errors_vs_oracle"] = oracle_errors(wl, p, xa, refs)
         del xa
         res[name] = r
     wall = time.perf_counter() - wall0
+    nsq = None
+    if args.nsqrt_steps > 0:
+        print("timing the FP64 form with the Newton-Schulz transform", file=sys.stderr, flush=True)
+        rate, ms, ph, launches, xa = timed_analyses(L, torch, wl, xb, obs, 0, args.nsqrt_steps, 1,
+                                                    L.LETKF_FLAG_NSQRT)
+        nsq = {"value": round(rate, 1), "ms_per_analysis": round(ms, 3),
+               "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+               "evd_route_fp64_ms": res["fp64"]["ms_per_analysis"],
+               "speedup_vs_evd_route": round(res["fp64"]["ms_per_analysis"] / ms, 3)}
+        if refs is not None:
+            nsq["errors_vs_oracle"] = oracle_errors(wl, p, xa, refs)
+        del xa
     head = res[args.precision]
     base = res["fp64"]
     for name in forms:
@@ -460,6 +516,8 @@ def main():
         "forms": res,
         "host_wall_s": round(wall, 3),
     }
+    if nsq is not None:
+        out["nsqrt_route_fp64"] = nsq
     del xb, obs
     torch.cuda.empty_cache()
     if args.secondary_steps > 0:

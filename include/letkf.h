@@ -114,6 +114,14 @@ typedef struct letkf_problem {
                                       call enqueues only kernels and, with OBS_ON_HOST and
                                       odd n_steps cycles, asynchronous copies: no allocation,
                                       memset or host synchronization */
+#define LETKF_FLAG_NSQRT        32 /* form the transform of eqs. letkf_wa / letkf_dwa without
+                                      the eigendecomposition: Q^-1/2 by the coupled
+                                      Newton-Schulz iteration on MFMA (as in
+                                      letkf_invsqrt_batched), wbar = Q^-1/2 (Q^-1/2 b), in
+                                      FP64 whatever the problem's precision form (which
+                                      still sets the Gram's).  Its cost grows with
+                                      log cond(Q), the EVD's does not; accuracy about
+                                      1e-17 cond(Q) relative */
 
 /* Plan options (pass NULL for the defaults: no budget, no flags, no cache). */
 typedef struct letkf_options {
@@ -287,6 +295,29 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
  */
 int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, double* vec,
                        int32_t* status, void* hip_stream);
+
+/*
+ * letkf_invsqrt_batched -- batched inverse square root of symmetric positive
+ * definite matrices, FP64, by the coupled Newton-Schulz iteration on MFMA:
+ * the direct route to the symmetric square root of eq. letkf_dwa
+ * (W = sqrt(k-1) Q^-1/2) that avoids the eigendecomposition, kept beside
+ * letkf_eigh_batched for the comparison of the two.
+ *   a:   device, [batch][k][k] symmetric positive definite (the full matrices
+ *        are read), 1 <= k <= LETKF_MAX_K;
+ *   x:   device, [batch][k][k] receives A^-1/2;
+ *   status: device int32 (may be NULL); bit (1 << LETKF_ENOTCONV) is OR-ed in
+ *        if a matrix's iteration did not converge (A not positive definite,
+ *        non-finite, or so ill-conditioned that 64 steps do not suffice: the
+ *        iteration takes about log_2.25(cond A) + 5 steps);
+ *   steps: device, [batch] int32 (may be NULL): the steps each matrix took
+ *        (each step is three k x k products, 6 k^3 flops).
+ * Accuracy: about 1e-17 cond(A) relative to ||A^-1/2||, which the status does
+ * not reflect; for the LETKF matrix cond(Q) <= 1 + rho lambda_max(C) / (k-1).
+ * Asynchronous on hip_stream.  Returns LETKF_EINVAL for bad sizes or NULL
+ * pointers.
+ */
+int letkf_invsqrt_batched(const double* a, int32_t batch, int32_t k, double* x,
+                          int32_t* status, int32_t* steps, void* hip_stream);
 
 /*
  * letkf_analyze_noalloc -- for callers that cannot allocate device memory

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libletkf.so")
 
 SOURCES = ["k_xf64.hip", "k_xf32.hip", "k_xf16.hip", "k_evd64.hip", "k_evd32.hip", "k_evd16.hip",
-           "k_gram.hip", "k_gram_lp.hip", "k_prep.hip", "k_lbm.hip", "api.cpp"]
+           "k_gram.hip", "k_gram_lp.hip", "k_prep.hip", "k_lbm.hip", "k_nsqrt.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 MAX_SCRATCH = 256   # bytes of private memory per lane a kernel may use

@@ -74,7 +74,7 @@ struct ProblemClass {
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 constexpr int kKnownFlags = LETKF_FLAG_PHASE_TIMING | LETKF_FLAG_CYCLE | LETKF_FLAG_OBS_ON_HOST |
-                            LETKF_FLAG_DETERMINISTIC | LETKF_FLAG_GRAPH_CAPTURE;
+                            LETKF_FLAG_DETERMINISTIC | LETKF_FLAG_GRAPH_CAPTURE | LETKF_FLAG_NSQRT;
 
 int check_problem(const letkf_problem& p) {
   if (p.nx < 1 || p.ny < 1 || p.nx > kMaxDim || p.ny > kMaxDim) return LETKF_EINVAL;
@@ -359,7 +359,9 @@ int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* 
     bm.n = std::min(slab, total - g0);
     if (launch_gram(bm, kp, prec, pl->gram_persistent, s) != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
-    if (launch_xf(bm, kp, s) != hipSuccess) return LETKF_EDEVICE;
+    const hipError_t rc = (pl->flags & LETKF_FLAG_NSQRT) ? launch_nsqrt_xf(bm, kp, s)
+                                                         : launch_xf(bm, kp, s);
+    if (rc != hipSuccess) return LETKF_EDEVICE;
     mk.at(mk.next++, s);
   }
   return LETKF_OK;
@@ -1119,6 +1121,17 @@ int letkf_eigh_batched(const double* a, int32_t batch, int32_t k, double* lam, d
   const int kp = pow2_at_least16(k);
   return launch_evd(bm, kp, static_cast<hipStream_t>(hip_stream)) == hipSuccess ? LETKF_OK
                                                                                  : LETKF_EDEVICE;
+}
+
+int letkf_invsqrt_batched(const double* a, int32_t batch, int32_t k, double* x,
+                          int32_t* status, int32_t* steps, void* hip_stream) {
+  if (batch < 0 || k < 1 || k > LETKF_MAX_K) return LETKF_EINVAL;
+  if (batch == 0) return LETKF_OK;
+  if (!a || !x) return LETKF_EINVAL;
+  return launch_nsqrt(a, batch, k, x, status, steps, static_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess
+             ? LETKF_OK
+             : LETKF_EDEVICE;
 }
 
 int letkf_analyze_noalloc(const letkf_problem* prob, const letkf_io* io, int32_t* status,

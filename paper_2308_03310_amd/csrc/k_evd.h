@@ -616,22 +616,6 @@ __device__ __forceinline__ void transform_update(const EvdArgs& e, EvdLds<KP>& s
   if (mine && !finite) atomicOr(e.status, kStatNonfinite);
 }
 
-// The descriptor of the problem that owns slab-local point pl, with C and b
-// pointed at the slab and pt0 set so that pt0 + pl is the point within its
-// problem (every helper indexes C, b by pl and the ensemble by pt0 + pl).
-__device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool& valid) {
-  valid = pl < bm.n;
-  const int gidx = bm.g0 + (valid ? pl : 0);
-  const int prob = bm.prefix ? find_problem(bm.prefix, bm.nprob, gidx) : 0;
-  EvdArgs e = bm.e ? bm.e[prob] : bm.e_inline;
-  e.C = bm.C;
-  e.b = bm.b;
-  e.pt0 = gidx - (bm.prefix ? bm.prefix[prob] : 0) - (valid ? pl : 0);
-  if (e.abort_flag && *e.abort_flag) valid = false;
-  return e;
-}
-
-
 template <int KP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WAVES))) void k_evd(BatchMap bm) {
   constexpr int G = 64 / KP;

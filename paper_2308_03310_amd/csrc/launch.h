@@ -141,6 +141,21 @@ __device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gi
   return lo;
 }
 
+// The descriptor of the problem that owns slab-local point pl, with C and b
+// pointed at the slab and pt0 set so that pt0 + pl is the point within its
+// problem (every helper indexes C, b by pl and the ensemble by pt0 + pl).
+__device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool& valid) {
+  valid = pl < bm.n;
+  const int gidx = bm.g0 + (valid ? pl : 0);
+  const int prob = bm.prefix ? find_problem(bm.prefix, bm.nprob, gidx) : 0;
+  EvdArgs e = bm.e ? bm.e[prob] : bm.e_inline;
+  e.C = bm.C;
+  e.b = bm.b;
+  e.pt0 = gidx - (bm.prefix ? bm.prefix[prob] : 0) - (valid ? pl : 0);
+  if (e.abort_flag && *e.abort_flag) valid = false;
+  return e;
+}
+
 // --- launchers (return hipError_t of the launch) ---
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
 hipError_t launch_clear_bits(int* p, int bits, hipStream_t s);
@@ -156,6 +171,9 @@ template <int KP>
 hipError_t launch_evd_kp(const BatchMap& bm, hipStream_t s);
 template <int KP>
 hipError_t launch_evd_xf_kp(const BatchMap& bm, hipStream_t s);
+hipError_t launch_nsqrt(const double* a, int batch, int k, double* x, int* status, int* steps,
+                        hipStream_t s);
+hipError_t launch_nsqrt_xf(const BatchMap& bm, int kp, hipStream_t s);
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
                       int force_kx, hipStream_t s);
 

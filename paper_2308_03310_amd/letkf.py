@@ -33,6 +33,7 @@ LETKF_FLAG_CYCLE = 2
 LETKF_FLAG_OBS_ON_HOST = 4
 LETKF_FLAG_DETERMINISTIC = 8
 LETKF_FLAG_GRAPH_CAPTURE = 16
+LETKF_FLAG_NSQRT = 32
 PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose")
 
 
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.letkf_phase_times.restype = ctypes.c_int
     lib.letkf_eigh_batched.argtypes = [dp, i32, i32, dp, dp, dp, vp]
     lib.letkf_eigh_batched.restype = ctypes.c_int
+    lib.letkf_invsqrt_batched.argtypes = [dp, i32, i32, dp, vp, vp, vp]
+    lib.letkf_invsqrt_batched.restype = ctypes.c_int
     lib.letkf_analyze_noalloc.argtypes = [ctypes.POINTER(letkf_problem), ctypes.POINTER(letkf_io),
                                           dp, vp]
     lib.letkf_analyze_noalloc.restype = ctypes.c_int
@@ -317,6 +320,26 @@ def letkf_eigh_batched(a, lam, vec, status=None, stream=None) -> int:
         _ptr(a, torch.float64), batch, k, _ptr(lam, torch.float64), _ptr(vec, torch.float64),
         _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
         "letkf_eigh_batched")
+
+
+def letkf_invsqrt_batched(a, x, status=None, steps=None, stream=None) -> int:
+    """a [batch, k, k] float64 SPD -> x = a^-1/2 [batch, k, k] (coupled
+    Newton-Schulz on MFMA); steps, if given, an int32 [batch] tensor that
+    receives each matrix's step count."""
+    import torch
+    batch, k = int(a.shape[0]), int(a.shape[-1])
+    if a.numel() != batch * k * k or x.numel() != batch * k * k:
+        raise ValueError(f"invsqrt_batched: a {tuple(a.shape)}, x {tuple(x.shape)} do not fit "
+                         f"batch {batch}, k {k}")
+    if status is not None and status.numel() < 1:
+        raise ValueError("invsqrt_batched: status needs one int32")
+    if steps is not None and steps.numel() < batch:
+        raise ValueError(f"invsqrt_batched: steps needs {batch} int32")
+    return _check(load_library().letkf_invsqrt_batched(
+        _ptr(a, torch.float64), batch, k, _ptr(x, torch.float64),
+        _ptr(status, torch.int32) if status is not None else None,
+        _ptr(steps, torch.int32) if steps is not None else None, _stream(stream)),
+        "letkf_invsqrt_batched")
 
 
 def letkf_analyze_noalloc(problem: letkf_problem, io: letkf_io, status, stream=None) -> int:

@@ -67,7 +67,7 @@ def test_plan_rejects_bad_options(lib):
     """Unknown flags, a nonzero reserved field and GRAPH_CAPTURE together
     with PHASE_TIMING are refused on the host, before any device call."""
     p = L.make_problem(**GOOD)
-    for flags in (32, 1 << 20, -1, L.LETKF_FLAG_GRAPH_CAPTURE | L.LETKF_FLAG_PHASE_TIMING):
+    for flags in (64, 1 << 20, -1, L.LETKF_FLAG_GRAPH_CAPTURE | L.LETKF_FLAG_PHASE_TIMING):
         rc, h = L.letkf_plan([p], flags=flags, raise_on_error=False)
         assert rc == L.LETKF_EINVAL and h is None, flags
     opt = L.letkf_options(0, 0, 1, None)
@@ -118,6 +118,9 @@ def test_null_handles(lib):
     assert lib.letkf_eigh_batched(None, 0, 8, None, None, None, None) == L.LETKF_OK
     assert lib.letkf_eigh_batched(None, 3, 8, None, None, None, None) == L.LETKF_EINVAL
     assert lib.letkf_analyze_noalloc(None, None, None, None) == L.LETKF_EINVAL
+    assert lib.letkf_invsqrt_batched(None, 4, 65, None, None, None, None) == L.LETKF_EINVAL
+    assert lib.letkf_invsqrt_batched(None, 0, 8, None, None, None, None) == L.LETKF_OK
+    assert lib.letkf_invsqrt_batched(None, 3, 8, None, None, None, None) == L.LETKF_EINVAL
 
 
 def test_noalloc_host_checks(lib):

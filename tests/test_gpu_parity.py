@@ -35,13 +35,14 @@ def dev_obs(p, torch):
 
 
 def gpu_analysis(p, L_len=None, infl=None, loc=L.LETKF_LOC_GAUSS, inplace=False, obs=True,
-                 var=None, xa_fill=None):
+                 var=None, xa_fill=None, flags=0):
     import torch
     wl = p.wl
     L_len = wl.L if L_len is None else L_len
     infl = wl.infl if infl is None else infl
     n_obs = len(p.obs_ix)
-    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, n_obs, L_len, infl, loc)])
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, n_obs, L_len, infl, loc)],
+                        flags=flags)
     try:
         xb = torch.from_numpy(p.xb).cuda()
         if inplace:
@@ -204,18 +205,25 @@ def _oracle_full(p, L_len=None, infl=None, loc=orc.LOC_GAUSS, var=None):
                               loc)
 
 
-def test_cpu32_k16_full_field():
+# the two routes to the transform: the eigendecomposition (default) and the
+# Newton-Schulz inverse square root (LETKF_FLAG_NSQRT)
+ROUTES = [0, L.LETKF_FLAG_NSQRT]
+
+
+@pytest.mark.parametrize("flags", ROUTES)
+def test_cpu32_k16_full_field(flags):
     p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
-    say("analysis cpu32_k16 (32x32, k=16) full field")
-    got, st = gpu_analysis(p)
+    say(f"analysis cpu32_k16 (32x32, k=16) full field flags={flags}")
+    got, st = gpu_analysis(p, flags=flags)
     assert st == L.LETKF_OK
     ref = _oracle_full(p)
     assert_parity(got, ref, TOL_FP64, p.xb, INC_TOL, "cpu32_k16")
 
 
+@pytest.mark.parametrize("flags", ROUTES)
 @pytest.mark.parametrize("loc", [orc.LOC_GAUSS, orc.LOC_GC, orc.LOC_NONE])
 @pytest.mark.parametrize("k", [5, 20, 40])
-def test_ragged_grid(loc, k):
+def test_ragged_grid(loc, k, flags):
     """Grid and ensemble sizes that are not multiples of any tile: 40 x 27
     lattice (ragged 64-point tiles and 8-point cells), obs of all three kinds
     on a stride-3 mask, L = 3.3 (window wraps around the periodic box for
@@ -223,8 +231,8 @@ def test_ragged_grid(loc, k):
     wl = synth.Workload("ragged", 40, 27, k, 3, 0.01, 3.3, 1.15, 40 + k,
                         kinds=(synth.OBS_RHO, synth.OBS_U, synth.OBS_V))
     p = synth.make_problem(wl)
-    say(f"analysis ragged 40x27 k={k} loc={loc}")
-    got, st = gpu_analysis(p, loc=loc)
+    say(f"analysis ragged 40x27 k={k} loc={loc} flags={flags}")
+    got, st = gpu_analysis(p, loc=loc, flags=flags)
     assert st == L.LETKF_OK
     ref = _oracle_full(p, loc=loc)
     assert_parity(got, ref, TOL_FP64, p.xb, INC_TOL, f"ragged k={k} loc={loc}")
@@ -252,23 +260,25 @@ def test_inplace_and_determinism():
     assert np.array_equal(a1, a3)
 
 
-def test_infinite_variance_returns_inflated_background():
+@pytest.mark.parametrize("flags", ROUTES)
+def test_infinite_variance_returns_inflated_background(flags):
     p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
-    say("analysis cpu32_k16 with every variance +inf")
+    say(f"analysis cpu32_k16 with every variance +inf flags={flags}")
     var = np.full_like(p.obs_var, np.inf)
-    got, st = gpu_analysis(p, var=var)
+    got, st = gpu_analysis(p, var=var, flags=flags)
     assert st == L.LETKF_OK
     xbar = p.xb.mean(axis=0, keepdims=True)
     ref = xbar + math.sqrt(p.wl.infl) * (p.xb - xbar)
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15)
-    got1, _ = gpu_analysis(p, var=var, infl=1.0)
+    got1, _ = gpu_analysis(p, var=var, infl=1.0, flags=flags)
     np.testing.assert_allclose(got1, p.xb, rtol=0, atol=1e-15)
 
 
-def test_no_observations():
+@pytest.mark.parametrize("flags", ROUTES)
+def test_no_observations(flags):
     p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
-    say("analysis cpu32_k16 with n_obs = 0")
-    got, st = gpu_analysis(p, obs=False, infl=1.0)
+    say(f"analysis cpu32_k16 with n_obs = 0 flags={flags}")
+    got, st = gpu_analysis(p, obs=False, infl=1.0, flags=flags)
     assert st == L.LETKF_OK
     np.testing.assert_allclose(got, p.xb, rtol=0, atol=1e-15)
 
@@ -299,17 +309,19 @@ def test_full_size_sampled(name, npts):
     wl = synth.WORKLOADS[name]
     say(f"generate {name}")
     p = synth.make_problem(wl)
-    say(f"analysis {name} ({wl.nx}x{wl.ny}, k={wl.k}) on the GPU")
-    got, st = gpu_analysis(p)
-    assert st == L.LETKF_OK
-    # properties at every point: analysis perturbations sum to zero
-    mean = got.mean(axis=0, keepdims=True)
-    assert np.abs((got - mean).sum(axis=0)).max() <= 1e-14 * wl.k
-    assert np.isfinite(got).all()
     pts = synth.sample_points(wl.nx, wl.ny, npts, seed=7)
     say(f"oracle on {len(pts)} sampled points")
     ref = orc.Analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
                        wl.infl).run(pts)
-    g = np.stack([got[:, :, q // wl.nx, q % wl.nx] for q in pts])
     xb = np.stack([p.xb[:, :, q // wl.nx, q % wl.nx] for q in pts])
-    assert_parity(g, ref, TOL_FP64, xb, INC_TOL, name)
+    for flags in ROUTES:
+        say(f"analysis {name} ({wl.nx}x{wl.ny}, k={wl.k}) on the GPU, flags={flags}")
+        got, st = gpu_analysis(p, flags=flags)
+        assert st == L.LETKF_OK
+        # properties at every point: analysis perturbations sum to zero
+        mean = got.mean(axis=0, keepdims=True)
+        assert np.abs((got - mean).sum(axis=0)).max() <= 1e-14 * wl.k
+        assert np.isfinite(got).all()
+        g = np.stack([got[:, :, q // wl.nx, q % wl.nx] for q in pts])
+        assert_parity(g, ref, TOL_FP64, xb, INC_TOL, f"{name} flags={flags}")
+        del got, g
