@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_GRAM_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 FORMS = (("fp64", 0), ("fp32", 1), ("bf16", 2))
 KERNEL_NAMES = {"gram": {"fp64": "k_gram_f64", "fp32": "k_gram_lp", "bf16": "k_gram_lp"},
-                "evd_update": "k_evd_xf"}
+                "evd_update": "k_evd_xf", "fused": "k_fused"}
 # Batched EVD of 16,384 matrices from the LBM-LETKF model on one A100 (FP32,
 # the paper's Table I, EigenG column): context for the eigensolve record.
 PAPER_TABLE1_EIGENG_MS = {16: 1.3, 32: 2.4, 48: 7.8, 64: 14.2}
@@ -106,15 +106,18 @@ def dev_obs(torch, p, dev):
                  (p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var))
 
 
-def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup, flags=0):
+def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup, flags=0, form=None):
     """steps whole analyses of one problem in one precision form on torch's
     current stream, bracketed by synchronizations: returns (analyses/s, ms per
-    analysis, per-phase ms per analysis, launches per phase, the analysis)."""
+    analysis, per-phase ms per analysis, launches per phase, the analysis).
+    form: a kernel form (LETKF_FORM_*) set on the plan, else its default."""
     xa = torch.empty_like(xb)
     plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, int(obs[0].numel()), wl.L, wl.infl,
                                         precision=precision)],
                         flags=L.LETKF_FLAG_PHASE_TIMING | flags)
     try:
+        if form is not None:
+            L.letkf_set_tuning(plan, 8, form)
         io = [L.make_io(0, xb, xa, obs)]
         stream = torch.cuda.current_stream()
         for _ in range(warmup):
@@ -144,20 +147,30 @@ def timed_analyses(L, torch, wl, xb, obs, precision, steps, warmup, flags=0):
 
 
 def kernel_roofline(wl, form, per_call, launches):
-    """Achieved rate of the Gram and eigensolve/update kernels: algorithmic
-    flops per launch over the average launch time from the HIP events."""
+    """Achieved rate of the Gram and eigensolve/update kernels (split forms)
+    or of the fused kernel: algorithmic flops per launch over the average
+    launch time from the HIP events.  The fused kernel does both kinds of
+    work, so its peak is the rate at which it would finish both at their own
+    peaks: (F_gram + F_evd) / (F_gram / P_gram + F_evd / P_fp64) -- the FP64
+    peak itself in the FP64 form."""
     flops = algorithmic_flops(wl)
     out = {}
-    for ph, bound, peak in (("gram", "mfma", PEAK_GRAM_TFLOPS[form]),
-                            ("evd_update", "alu", PEAK_FP64_TFLOPS)):
+    if launches.get("fused", 0) > 0:
+        fg, fe = flops["gram"], flops["evd_update"]
+        peak = (fg + fe) / (fg / PEAK_GRAM_TFLOPS[form] + fe / PEAK_FP64_TFLOPS)
+        phases = (("fused", "alu", round(peak, 3), fg + fe),)
+    else:
+        phases = (("gram", "mfma", PEAK_GRAM_TFLOPS[form], flops["gram"]),
+                  ("evd_update", "alu", PEAK_FP64_TFLOPS, flops["evd_update"]))
+    for ph, bound, peak, fl in phases:
         n_l = max(launches[ph], 1)
         ms_launch = per_call[ph] / n_l
-        ach = flops[ph] / n_l / (ms_launch / 1e3) / 1e12
+        ach = fl / n_l / (ms_launch / 1e3) / 1e12
         name = KERNEL_NAMES[ph][form] if isinstance(KERNEL_NAMES[ph], dict) else KERNEL_NAMES[ph]
         out[ph] = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
                    "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                    "ms_per_launch": round(ms_launch, 4), "launches_per_step": n_l,
-                   "flops_per_launch": flops[ph] / n_l}
+                   "flops_per_launch": fl / n_l}
     return out
 
 
@@ -403,6 +416,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary-steps", type=int, default=10,
                     help="timed steps of the 256^2, k = 32 FP64 workload (0 to skip)")
+    ap.add_argument("--split-steps", type=int, default=3,
+                    help="analyses timed in the split kernel form (Gram and eigensolve "
+                         "launches per slab) for the FP64 and headline forms (0: skip)")
     ap.add_argument("--nsqrt-steps", type=int, default=3,
                     help="analyses timed with the Newton-Schulz route to the transform "
                          "(LETKF_FLAG_NSQRT, FP64 form) beside the EVD route (0: skip)")
@@ -421,6 +437,8 @@ def main():
     ap.add_argument("--batching-precision", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision form of the mixed batch (its recipe names the FP32 path)")
     ap.add_argument("--batching-reps", type=int, default=2)
+    ap.add_argument("--batching-small-problems", type=int, default=256,
+                    help="problems of the small-lattice batch (64 x 64 only; 0: skip)")
     ap.add_argument("--batching-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -477,15 +495,31 @@ def main():
         if refs is not None:
             nsq["errors_vs_oracle"] = oracle_errors(wl, p, xa, refs)
         del xa
+    # the split kernel form (a Gram and an eigensolve launch per slab) of the
+    # FP64 form and the headline form: the per-kernel breakdown the fused
+    # launch cannot give, and the fused form's gain over it
+    split = {}
+    for name in (["fp64", args.precision] if args.split_steps > 0 else []):
+        if name in split:
+            continue
+        print(f"timing the {name} form, split kernels", file=sys.stderr, flush=True)
+        rate, ms, ph, launches, xa = timed_analyses(L, torch, wl, xb, obs, dict(FORMS)[name],
+                                                    args.split_steps, 1, form=L.LETKF_FORM_GRID)
+        del xa
+        split[name] = {"value": round(rate, 1), "ms_per_analysis": round(ms, 3),
+                       "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+                       "kernels": kernel_roofline(wl, name, ph, launches),
+                       "fused_speedup": round(ms / res[name]["ms_per_analysis"], 3)}
+    if "fp64" in split and args.precision in split and args.precision != "fp64":
+        split[args.precision]["gram_speedup_vs_fp64"] = round(
+            split["fp64"]["phases_ms"]["gram"] / split[args.precision]["phases_ms"]["gram"], 3)
     head = res[args.precision]
     base = res["fp64"]
     for name in forms:
         if name != "fp64":
             res[name]["speedup_vs_fp64"] = round(res[name]["value"] / base["value"], 3)
-            res[name]["gram_speedup_vs_fp64"] = round(
-                base["phases_ms"]["gram"] / res[name]["phases_ms"]["gram"], 3)
 
-    dom = max(("gram", "evd_update"), key=lambda ph: head["phases_ms"][ph])
+    dom = max(head["kernels"], key=lambda ph: head["phases_ms"][ph])
     kd = head["kernels"][dom]
     roof = {k: kd[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
     roof["kernel"] = kd["kernel"]
@@ -509,11 +543,14 @@ def main():
                    "L": wl.L, "infl": wl.infl, "sigma": wl.sigma,
                    "precision": f"{args.precision} Gram/update contractions (FP32 accumulation), "
                                 f"fp64 eigensolve and eigenvalue scaling",
-                   "localization": "gauss(2L cutoff)"},
+                   "localization": "gauss(2L cutoff)",
+                   "kernel_form": "auto: fused at this width (Gram, eigensolve, transform "
+                                  "and update of every point in one persistent launch)"},
         "speedup_vs_fp64": head["speedup_vs_fp64"],
         "fp64_value": base["value"],
         "roofline": roof,
         "forms": res,
+        "split_kernel_form": split,
         "host_wall_s": round(wall, 3),
     }
     if nsq is not None:
@@ -562,6 +599,14 @@ def main():
                                              tuple(int(g) for g in args.batching_grids.split(",")),
                                              args.batching_precision, args.batching_reps,
                                              args.batching_tune)
+    if args.batching_small_problems > 0:
+        # the same recipe restricted to 64 x 64 lattices: problems too small to
+        # fill the device alone, where one call each leaves it idle between
+        # launches and a batched call does not
+        print("batching form, small problems", file=sys.stderr, flush=True)
+        out["batching_form_small"] = batching_form(L, torch, args.batching_small_problems, (64,),
+                                                   args.batching_precision, args.batching_reps,
+                                                   False)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

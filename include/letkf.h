@@ -210,20 +210,33 @@ int letkf_advance(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, voi
  * letkf_tune -- project autotuner for the plan's launch settings.  Runs the
  * analyses io[0..n_io) (every problem once gives the batched form) with each
  * candidate setting -- observation-cell edge 4, 8 or 16 lattice points (the
- * tile of the local-observation search) x the Gram kernels in grid or
- * persistent work-queue form -- times each on hip_stream with HIP events, and
+ * tile of the local-observation search) x the kernel form (LETKF_FORM_*) --
+ * times each on hip_stream with HIP events, and
  * keeps the fastest in the plan for later letkf_analyze / letkf_cycle calls.
  * Synchronizes the stream (not usable under graph capture).  On return the
  * outputs hold one analysis made with the chosen setting; out (may be NULL)
- * receives it.  With LETKF_FLAG_DETERMINISTIC only the Gram form is timed and
- * the cell edge keeps its default.  With a tune_cache_path the choice is
+ * receives it.  With LETKF_FLAG_DETERMINISTIC only the kernel form is timed
+ * and the cell edge keeps its default.  With a tune_cache_path the choice is
  * recorded in that file under a key of the problem list and device (the
  * setting still applies if that fails, and LETKF_EIO is returned).  Errors as
  * letkf_analyze, plus LETKF_EDEVICE.
  */
+/* Kernel forms of the Gram -> eigensolve -> update steps (letkf_tuning.form);
+ * a plan starts in LETKF_FORM_AUTO (or the form its tuning cache names). */
+#define LETKF_FORM_GRID       0  /* a Gram launch and an eigensolve launch per slab of points */
+#define LETKF_FORM_PERSISTENT 1  /* the same, the Gram launches as persistent work queues */
+#define LETKF_FORM_FUSED      2  /* one persistent launch per width class doing the Gram,
+                                    eigensolve, transform and update of every point of the
+                                    call's problems, C kept in a per-wavefront slot in L2;
+                                    problems ordered by estimated cost, dearest first
+                                    (plans with LETKF_FLAG_NSQRT run it as GRID) */
+#define LETKF_FORM_AUTO       3  /* FUSED for the problems with 33 <= k <= 64, GRID for the
+                                    narrower ones (where the Gram's own occupancy matters
+                                    more than C's round trip through HBM) */
+
 typedef struct letkf_tuning {
   int32_t cell;             /* observation-cell edge chosen */
-  int32_t gram_persistent;  /* 1: Gram kernels in persistent form */
+  int32_t form;             /* LETKF_FORM_* */
   double  ms_per_call;      /* measured time of one call with that setting */
 } letkf_tuning;
 
@@ -232,11 +245,12 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_st
 
 /*
  * letkf_set_tuning -- apply a setting (from letkf_tune, e.g. kept from an
- * earlier run) without timing anything: cell in {4, 8, 16}, gram_persistent
- * in {0, 1}; ms_per_call is ignored.  Waits for the plan's last stream.
+ * earlier run) without timing anything: cell in {4, 8, 16}, form one of
+ * LETKF_FORM_* (letkf_tune reports GRID, PERSISTENT or FUSED); ms_per_call
+ * is ignored.  Waits for the plan's last stream.
  * Returns LETKF_EINVAL for other values.  Results depend on the cell edge
  * only through the summation order of the Gram matrix (rounding level); the
- * two Gram forms give bitwise-identical results.
+ * three forms give bitwise-identical results.
  */
 int letkf_set_tuning(letkf_plan_t plan, const letkf_tuning* t);
 
@@ -267,7 +281,8 @@ uint64_t letkf_plan_workspace_bytes(letkf_plan_t plan);
 #define LETKF_PHASE_GRAM       3  /* localized Gram matrix and right-hand side */
 #define LETKF_PHASE_EVD        4  /* eigensolve, transform, update */
 #define LETKF_PHASE_UNTRANS    5  /* point-major -> member-major analysis */
-#define LETKF_N_PHASES         6
+#define LETKF_PHASE_FUSED      6  /* Gram + eigensolve + update in one launch (the fused form) */
+#define LETKF_N_PHASES         7
 
 /*
  * letkf_phase_times -- for a plan made with LETKF_FLAG_PHASE_TIMING: waits for

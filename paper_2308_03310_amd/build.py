@@ -18,8 +18,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libletkf.so")
 
-SOURCES = ["k_xf64.hip", "k_xf32.hip", "k_xf16.hip", "k_evd64.hip", "k_evd32.hip", "k_evd16.hip",
-           "k_gram.hip", "k_gram_lp.hip", "k_prep.hip", "k_lbm.hip", "k_nsqrt.hip", "api.cpp"]
+SOURCES = ["k_fused64.hip", "k_fused32.hip", "k_fused16.hip", "k_xf64.hip", "k_xf32.hip",
+           "k_xf16.hip", "k_evd64.hip", "k_evd32.hip", "k_evd16.hip", "k_gram.hip", "k_gram_lp.hip",
+           "k_prep.hip", "k_lbm.hip", "k_nsqrt.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 MAX_SCRATCH = 256   # bytes of private memory per lane a kernel may use
@@ -29,6 +30,14 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
+
+
+# Per-source additions.  The fused kernels' persistent item loop: machine
+# loop-invariant code motion would hoist the per-lane arithmetic of the whole
+# loop body (Gram and eigensolve) out of it and keep it live throughout
+# (register spills); the sources also make the lane index opaque for the same
+# reason at the IR level.
+EXTRA = {f"k_fused{k}.hip": ["-mllvm", "-disable-machine-licm"] for k in (16, 32, 64)}
 
 
 def _compile(src: str, force: bool) -> str:
@@ -41,7 +50,8 @@ def _compile(src: str, force: bool) -> str:
                      os.path.getmtime(os.path.join(ROOT, "include", "letkf.h")))
         if os.path.getmtime(obj) >= newest:
             return obj
-    cmd = [HIPCC] + FLAGS + ["-Rpass-analysis=kernel-resource-usage", "-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-Rpass-analysis=kernel-resource-usage", "-c",
+                                                  path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")

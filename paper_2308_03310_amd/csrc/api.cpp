@@ -143,7 +143,7 @@ struct letkf_plan_s {
   uint64_t bytes = 0;
   std::atomic<int> busy{0};
   hipStream_t last_stream = nullptr;
-  bool gram_persistent = false;     // Gram kernels in their persistent form (tunable)
+  int form = LETKF_FORM_AUTO;       // kernel form of the Gram -> update steps (tunable)
   int* queue = nullptr;             // device [kQueueSlots]: persistent-launch work counters
   // Phase timing: a ring of event sets, one set per timed call.
   static constexpr int kSlots = 256;
@@ -151,6 +151,8 @@ struct letkf_plan_s {
   int nev = 0;                      // events per slot
   std::vector<hipEvent_t> ev;       // kSlots * nev
   std::vector<int> slot_slabs;      // slabs launched in the slot's call
+  int max_pairs = 0;                // launch pairs (Gram, eigensolve) per call, at most
+  std::vector<char> pair_fused;     // kSlots * max_pairs: the pair was one fused launch
   int next_slot = 0, recorded = 0;
 
   template <class T>
@@ -314,6 +316,13 @@ hipError_t launch_evd(const BatchMap& bm, int kp, hipStream_t s) {
 
 // Eigensolve + transform + update of an analysis (the eigenvectors are never
 // formed).
+hipError_t launch_fused(const BatchMap& bm, int kp, int prec, hipStream_t s) {
+  if (kp == 16) return launch_fused_kp<16>(bm, prec, s);
+  if (kp == 32) return launch_fused_kp<32>(bm, prec, s);
+  if (kp == 64) return launch_fused_kp<64>(bm, prec, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_xf(const BatchMap& bm, int kp, hipStream_t s) {
   if (kp == 16) return launch_evd_xf_kp<16>(bm, s);
   if (kp == 32) return launch_evd_xf_kp<32>(bm, s);
@@ -321,14 +330,30 @@ hipError_t launch_xf(const BatchMap& bm, int kp, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// Whether a width class runs in the fused form.
+bool fused_form(const letkf_plan_s* pl, int kp) {
+  if (pl->flags & LETKF_FLAG_NSQRT) return false;
+  return pl->form == LETKF_FORM_FUSED || (pl->form == LETKF_FORM_AUTO && kp == 64);
+}
+
+// Launch pairs per call of the Gram -> update steps over total points.
+int step_launches(const letkf_plan_s* pl, int kp, int total, int slab) {
+  return fused_form(pl, kp) ? 1 : ceil_div(total, slab);
+}
+
 // Timing marks of one call: [0] start, [1] after binning, [2] after the
 // transposes, [3] after the forecast observations, then (Gram, eigensolve)
 // per slab, then the end.
 struct Marks {
   hipEvent_t* ev = nullptr;
+  char* fused = nullptr;      // per launch pair of the call: one fused launch
   int next = 4;
   void at(int i, hipStream_t s) const {
     if (ev) (void)hipEventRecord(ev[i], s);
+  }
+  // the pair that starts at the next mark is a fused launch
+  void set_fused() const {
+    if (fused) fused[(next - 4) / 2] = 1;
   }
 };
 
@@ -339,11 +364,14 @@ Marks begin_timed(letkf_plan_s* pl, int nslabs) {
   pl->next_slot = (pl->next_slot + 1) % letkf_plan_s::kSlots;
   if (pl->recorded < letkf_plan_s::kSlots) ++pl->recorded;
   m.ev = &pl->ev[(size_t)slot * pl->nev];
+  m.fused = &pl->pair_fused[(size_t)slot * pl->max_pairs];
+  std::fill(m.fused, m.fused + pl->max_pairs, 0);
   pl->slot_slabs[slot] = nslabs;
   return m;
 }
 
-// Gram + eigensolve over the slabs of a problem table (a class or one problem).
+// Gram + eigensolve over the slabs of a problem table (a class or one problem),
+// or the fused launch over all of it.
 int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* prefix, int nprob,
               int total, int kp, int prec, int slab, hipStream_t s, Marks& mk) {
   BatchMap bm{};
@@ -354,10 +382,21 @@ int run_slabs(letkf_plan_s* pl, const GramArgs* g, const EvdArgs* e, const int* 
   bm.C = pl->slab_C;
   bm.b = pl->slab_b;
   bm.queue = pl->queue;
+  if (fused_form(pl, kp)) {
+    // one launch over every point; the Gram mark then closes an empty phase
+    bm.g0 = 0;
+    bm.n = total;
+    mk.set_fused();
+    mk.at(mk.next++, s);
+    if (launch_fused(bm, kp, prec, s) != hipSuccess) return LETKF_EDEVICE;
+    mk.at(mk.next++, s);
+    return LETKF_OK;
+  }
   for (int g0 = 0; g0 < total; g0 += slab) {
     bm.g0 = g0;
     bm.n = std::min(slab, total - g0);
-    if (launch_gram(bm, kp, prec, pl->gram_persistent, s) != hipSuccess) return LETKF_EDEVICE;
+    if (launch_gram(bm, kp, prec, pl->form == LETKF_FORM_PERSISTENT, s) != hipSuccess)
+      return LETKF_EDEVICE;
     mk.at(mk.next++, s);
     const hipError_t rc = (pl->flags & LETKF_FLAG_NSQRT) ? launch_nsqrt_xf(bm, kp, s)
                                                          : launch_xf(bm, kp, s);
@@ -379,6 +418,18 @@ int check_io(const letkf_plan_s* pl, const letkf_io& io) {
 }
 
 int single_slab(const ProblemWs& w) { return slab_points(w.nb, w.kp, w.npts); }
+
+// Estimated cost of one grid point of a problem, in FP64 flop: the Gram over
+// its expected local observations (the observation density at n_obs_max
+// times the window area) and the eigensolve and update (11 KP^3).
+double point_cost(const ProblemWs& w) {
+  const letkf_problem& p = w.p;
+  const double dens = (double)p.n_obs_max / ((double)p.nx * p.ny);
+  const double side = p.loc == LETKF_LOC_NONE ? 1e30 : 4.0 * p.loc_len + 1.0;
+  const double area = std::min(side * side, (double)p.nx * p.ny);
+  const double kp = (double)w.kp;
+  return dens * area * kp * (kp + 1.0) + 11.0 * kp * kp * kp;
+}
 
 // Analyses of n_io problems; src[i] is the member-major background of io[i]
 // (io[i].xb, or the cycle's ping-pong buffer).  batched: every problem of the
@@ -412,7 +463,7 @@ int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int 
   int rc = LETKF_OK;
   if (batched) {
     int nslabs = 0;
-    for (const ProblemClass& c : pl->classes) nslabs += ceil_div(c.total, c.slab);
+    for (const ProblemClass& c : pl->classes) nslabs += step_launches(pl, c.kp, c.total, c.slab);
     Marks mk = begin_timed(pl, nslabs);
     mk.at(0, s);
     for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_bin(i);
@@ -433,7 +484,7 @@ int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int 
   for (int i = 0; i < n_io && rc == LETKF_OK; ++i) {
     const int p = io[i].problem;
     const ProblemWs& w = pl->probs[p];
-    Marks mk = i == 0 ? begin_timed(pl, ceil_div(w.npts, single_slab(w))) : Marks{};
+    Marks mk = i == 0 ? begin_timed(pl, step_launches(pl, w.kp, w.npts, single_slab(w))) : Marks{};
     mk.at(0, s);
     rc = prep_bin(i);
     mk.at(1, s);
@@ -559,7 +610,7 @@ int device_ios(const letkf_plan_s* pl, const letkf_io* io, int n_io, hipStream_t
 }
 
 // ---- tuning cache (letkf_options.tune_cache_path) ----
-// One line per entry: "<key> <cell> <gram_persistent> <ms_per_call>", key =
+// One line per entry: "<key> <cell> <form> <ms_per_call>", key =
 // 64-bit FNV-1a of the problem list and the device's architecture and CU
 // count, in hex.  The last line with a key wins.
 
@@ -578,7 +629,7 @@ uint64_t tune_key(const letkf_plan_s* pl) {
   return h;
 }
 
-bool load_tune_cache(const letkf_plan_s* pl, int* cell, int* persistent) {
+bool load_tune_cache(const letkf_plan_s* pl, int* cell, int* form) {
   if (pl->cache_path.empty()) return false;
   FILE* f = std::fopen(pl->cache_path.c_str(), "r");
   if (!f) return false;
@@ -590,9 +641,9 @@ bool load_tune_cache(const letkf_plan_s* pl, int* cell, int* persistent) {
     int c = 0, pe = 0;
     double ms = 0.0;
     if (std::sscanf(line, "%llx %d %d %lf", &k, &c, &pe, &ms) == 4 && k == key &&
-        (c == 4 || c == 8 || c == 16) && (pe == 0 || pe == 1)) {
+        (c == 4 || c == 8 || c == 16) && pe >= LETKF_FORM_GRID && pe <= LETKF_FORM_AUTO) {
       *cell = c;
-      *persistent = pe;
+      *form = pe;
       found = true;
     }
   }
@@ -600,7 +651,7 @@ bool load_tune_cache(const letkf_plan_s* pl, int* cell, int* persistent) {
   return found;
 }
 
-bool save_tune_cache(const letkf_plan_s* pl, int cell, int persistent, double ms) {
+bool save_tune_cache(const letkf_plan_s* pl, int cell, int form, double ms) {
   const uint64_t key = tune_key(pl);
   std::vector<std::string> keep;
   if (FILE* f = std::fopen(pl->cache_path.c_str(), "r")) {
@@ -617,8 +668,7 @@ bool save_tune_cache(const letkf_plan_s* pl, int cell, int persistent, double ms
   if (!f) return false;
   bool ok = true;
   for (const std::string& l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
-  ok = ok && std::fprintf(f, "%016llx %d %d %.6f\n", (unsigned long long)key, cell, persistent,
-                          ms) > 0;
+  ok = ok && std::fprintf(f, "%016llx %d %d %.6f\n", (unsigned long long)key, cell, form, ms) > 0;
   ok = (std::fclose(f) == 0) && ok;
   return ok && std::rename(tmp.c_str(), pl->cache_path.c_str()) == 0;
 }
@@ -763,6 +813,13 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     classes[c].members.push_back(i);
     classes[c].total += ws[i].npts;
   }
+  // members dearest per point first: the fused form's queues then hand out
+  // the expensive points early and the cheap ones fill the tail (the order
+  // changes no result; every point is independent)
+  for (auto& c : classes)
+    std::stable_sort(c.members.begin(), c.members.end(), [&](int a, int b) {
+      return point_cost(ws[a]) > point_cost(ws[b]);
+    });
   // slab buffers: the largest slab of any class or single problem
   uint64_t c_doubles = 0, b_doubles = 0;
   for (auto& c : classes) {
@@ -774,6 +831,9 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
     const uint64_t sl = (uint64_t)single_slab(w);
     c_doubles = std::max(c_doubles, sl * w.nb * 256);
     b_doubles = std::max(b_doubles, sl * w.kp);
+    // the fused form's slots: one per block of its device-filling launch
+    c_doubles = std::max(c_doubles, (uint64_t)kFusedBlocks * fused_slot_c(w.kp));
+    b_doubles = std::max(b_doubles, (uint64_t)kFusedBlocks * fused_slot_b(w.kp));
   }
   uint64_t total = 4096 + (c_doubles + b_doubles) * sizeof(double);
   for (auto& w : ws) total += ws_bytes(w, cycle, host_obs);
@@ -818,11 +878,11 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
   }
   // a setting recorded by an earlier letkf_tune for the same problems and device
   if (ok) {
-    int cell = kCell, pers = 0;
-    if (load_tune_cache(pl, &cell, &pers)) {
+    int cell = kCell, form = LETKF_FORM_AUTO;
+    if (load_tune_cache(pl, &cell, &form)) {
       if (flags & LETKF_FLAG_DETERMINISTIC) cell = kCell;
       for (auto& w : pl->probs) set_cell(w, cell);
-      pl->gram_persistent = pers == 1;
+      pl->form = form;
     }
   }
   ok = ok && pl->alloc(&pl->slab_C, (size_t)c_doubles) && pl->alloc(&pl->slab_b, (size_t)b_doubles);
@@ -836,12 +896,14 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
   ok = ok && upload_descriptors(pl);
   if (ok && opt && (opt->flags & LETKF_FLAG_PHASE_TIMING)) {
     int max_slabs = 0;
-    for (auto& c : pl->classes) max_slabs += ceil_div(c.total, c.slab);
+    for (auto& c : pl->classes) max_slabs += ceil_div(c.total, c.slab);   // >= the fused form's
     for (auto& w : pl->probs) max_slabs = std::max(max_slabs, ceil_div(w.npts, single_slab(w)));
     pl->timing = true;
     pl->nev = 5 + 2 * max_slabs;
     pl->ev.resize((size_t)letkf_plan_s::kSlots * pl->nev);
     pl->slot_slabs.assign(letkf_plan_s::kSlots, 0);
+    pl->max_pairs = max_slabs;
+    pl->pair_fused.assign((size_t)letkf_plan_s::kSlots * max_slabs, 0);
     for (auto& e : pl->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
   }
   if (!ok || hipMemset(pl->stat, 0, (2 + (size_t)n_probs) * sizeof(int)) != hipSuccess ||
@@ -960,14 +1022,16 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io_in, int32_t n_io, void* hip
   constexpr int kReps = 2;
   double best_ms = 0.0;
   int best_cell = kCell;
-  bool best_persist = false;
+  int best_form = LETKF_FORM_GRID;
   bool have = false;
-  // DETERMINISTIC: only the Gram form, which leaves every bit unchanged
+  // DETERMINISTIC: only the kernel form, which leaves every bit unchanged;
+  // NSQRT plans have no fused form
   const bool det = plan->flags & LETKF_FLAG_DETERMINISTIC;
+  const int nforms = (plan->flags & LETKF_FLAG_NSQRT) ? 2 : 3;
   for (int ci = det ? 1 : 0; ci < (det ? 2 : 3) && rc == LETKF_OK; ++ci) {
-    for (int pi = 0; pi < 2 && rc == LETKF_OK; ++pi) {
+    for (int pi = 0; pi < nforms && rc == LETKF_OK; ++pi) {
       for (auto& w : plan->probs) set_cell(w, kCells[ci]);
-      plan->gram_persistent = pi == 1;
+      plan->form = pi;
       if (!upload_descriptors(plan)) {
         rc = LETKF_EDEVICE;
         break;
@@ -984,12 +1048,12 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io_in, int32_t n_io, void* hip
         have = true;
         best_ms = ms / kReps;
         best_cell = kCells[ci];
-        best_persist = pi == 1;
+        best_form = pi;
       }
     }
   }
   for (auto& w : plan->probs) set_cell(w, best_cell);
-  plan->gram_persistent = best_persist;
+  plan->form = best_form;
   if (!upload_descriptors(plan) && rc == LETKF_OK) rc = LETKF_EDEVICE;
   if (rc == LETKF_OK) {
     // leave the outputs as one plain analysis with the chosen settings would
@@ -1002,11 +1066,11 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io_in, int32_t n_io, void* hip
   plan->last_stream = s;
   if (rc == LETKF_OK && out) {
     out->cell = best_cell;
-    out->gram_persistent = best_persist ? 1 : 0;
+    out->form = best_form;
     out->ms_per_call = best_ms;
   }
   if (rc == LETKF_OK && !plan->cache_path.empty() &&
-      !save_tune_cache(plan, best_cell, best_persist ? 1 : 0, best_ms))
+      !save_tune_cache(plan, best_cell, best_form, best_ms))
     rc = LETKF_EIO;
   plan->busy.store(0);
   return rc;
@@ -1015,14 +1079,14 @@ int letkf_tune(letkf_plan_t plan, const letkf_io* io_in, int32_t n_io, void* hip
 int letkf_set_tuning(letkf_plan_t plan, const letkf_tuning* t) {
   if (!plan || !t) return LETKF_EINVAL;
   if (t->cell != 4 && t->cell != 8 && t->cell != 16) return LETKF_EINVAL;
-  if (t->gram_persistent != 0 && t->gram_persistent != 1) return LETKF_EINVAL;
+  if (t->form < LETKF_FORM_GRID || t->form > LETKF_FORM_AUTO) return LETKF_EINVAL;
   int expect = 0;
   if (!plan->busy.compare_exchange_strong(expect, 1)) return LETKF_EBUSY;
   DeviceGuard guard(plan->device);
   int rc = hipStreamSynchronize(plan->last_stream) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
   if (rc == LETKF_OK) {
     for (auto& w : plan->probs) set_cell(w, t->cell);
-    plan->gram_persistent = t->gram_persistent == 1;
+    plan->form = t->form;
     if (!upload_descriptors(plan)) rc = LETKF_EDEVICE;
   }
   plan->busy.store(0);
@@ -1067,14 +1131,15 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
   if (!plan->timing) return -LETKF_EINVAL;
   DeviceGuard guard(plan->device);
   if (hipStreamSynchronize(plan->last_stream) != hipSuccess) return -LETKF_EDEVICE;
-  double acc[LETKF_N_PHASES] = {0, 0, 0, 0, 0, 0};
-  int last_slabs = 0;
+  double acc[LETKF_N_PHASES] = {0, 0, 0, 0, 0, 0, 0};
+  int last_split = 0, last_fused = 0;
   const int calls = plan->recorded;
   for (int c = 0; c < calls; ++c) {
     const int slot = (plan->next_slot - 1 - c + 2 * letkf_plan_s::kSlots) % letkf_plan_s::kSlots;
     const hipEvent_t* ev = &plan->ev[(size_t)slot * plan->nev];
     const int nsl = plan->slot_slabs[slot];
-    last_slabs = nsl;
+    const char* fused = &plan->pair_fused[(size_t)slot * plan->max_pairs];
+    last_split = last_fused = 0;
     float t = 0.f;
     auto el = [&](int a, int b) -> double {
       return hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess ? (double)t : 0.0;
@@ -1084,14 +1149,21 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
     acc[LETKF_PHASE_OBSOP] += el(2, 3);
     int prev = 3;
     for (int ci = 0; ci < nsl; ++ci) {
-      acc[LETKF_PHASE_GRAM] += el(prev, 4 + 2 * ci);
-      acc[LETKF_PHASE_EVD] += el(4 + 2 * ci, 5 + 2 * ci);
+      if (fused[ci]) {
+        acc[LETKF_PHASE_FUSED] += el(prev, 5 + 2 * ci);
+        ++last_fused;
+      } else {
+        ++last_split;
+        acc[LETKF_PHASE_GRAM] += el(prev, 4 + 2 * ci);
+        acc[LETKF_PHASE_EVD] += el(4 + 2 * ci, 5 + 2 * ci);
+      }
       prev = 5 + 2 * ci;
     }
     acc[LETKF_PHASE_UNTRANS] += el(prev, 4 + 2 * nsl);
   }
   const int bin_launches = 5;  // two fills, count, scan, scatter + sort
-  const int per_call[LETKF_N_PHASES] = {bin_launches, 1, 1, last_slabs, last_slabs, 1};
+  const int per_call[LETKF_N_PHASES] = {bin_launches, 1, 1, last_split, last_split, 1,
+                                        last_fused};
   for (int i = 0; i < n; ++i) {
     ms[i] = i < LETKF_N_PHASES ? acc[i] : 0.0;
     if (launches) launches[i] = i < LETKF_N_PHASES ? per_call[i] : 0;

@@ -28,7 +28,18 @@ constexpr int kStatNotconv = 1 << 6;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+// The lane's index in its wavefront.  A translation unit that defines
+// LETKF_OPAQUE_LANE before its includes gets it as a fresh value at every
+// call (an empty asm), so that nothing computed from it can be hoisted out
+// of a loop (the fused persistent kernel's item loop: hoisted per-lane
+// addresses of the loop body would stay live through all of it).
+__device__ __forceinline__ int lane_id() {
+  int l = (int)__lane_id();
+#ifdef LETKF_OPAQUE_LANE
+  asm volatile("" : "+v"(l));
+#endif
+  return l;
+}
 
 // *p copied into scalar registers (the fields are read per lane, then taken
 // from the first lane): for a descriptor whose address is uniform but whose

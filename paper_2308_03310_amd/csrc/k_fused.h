@@ -1,0 +1,97 @@
+// The fused form of an analysis: the localized Gram matrix (k_gram.h,
+// k_gram_lp.h), the eigensolve, transform and update (k_xf.h) of every point
+// of one or several problems in one persistent launch.
+//
+// Each block is one wavefront that takes items of 64 / KP consecutive points
+// from the per-XCD work queues (neighbouring points share observations, so an
+// XCD's L2 keeps serving them), forms the items' C and b one point after
+// another into its own slot of global memory, then runs the eigensolve and
+// update on the item, one point per KP lanes.  The slot is written and read
+// back by the same wavefront right away, so C stays in the L2 instead of
+// making the round trip through HBM that separate Gram and eigensolve
+// launches need, and the whole analysis is one launch of device-filling
+// size instead of two launches per slab.  The Gram's gathers and the FP64
+// eigensolve of the other wavefronts on a SIMD overlap.  The arithmetic is
+// that of the separate kernels, so results are bitwise the same.
+#pragma once
+#include "common.h"
+#include "launch.h"
+#include "k_gram.h"
+#include "k_gram_lp.h"
+#include "k_xf.h"
+
+namespace letkf {
+
+template <int KP>
+struct FusedLds {
+  union {
+    struct {                      // the Gram's ring of local observations
+      int s[kRing];
+      double w[kRing];
+    } ring;
+    XfLds<KP> xf;
+  };
+};
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fused(BatchMap bm) {
+  constexpr int G = 64 / KP;
+  constexpr int NQ = KP / 16, NB = NQ * (NQ + 1) / 2;
+  __shared__ FusedLds<KP> sh;
+  const int lane = lane_id();
+  const int seg = lane / KP, jj = lane % KP;
+  double* slot_c = bm.C + (size_t)blockIdx.x * fused_slot_c(KP);
+  double* slot_b = bm.b + (size_t)blockIdx.x * fused_slot_b(KP);
+  const int nitems = (bm.n + G - 1) / G;
+  for_each_queued(bm.queue, nitems, [&](int item) __attribute__((always_inline)) {
+    const int p0 = item * G;
+#pragma unroll 1
+    for (int u = 0; u < G; ++u) {
+      if (p0 + u < bm.n) {                     // uniform
+        if constexpr (PREC == 0)
+          gram_f64_point<KP>(bm, p0 + u, sh.ring.s, sh.ring.w, slot_c + u * NB * 256,
+                             slot_b + u * KP);
+        else
+          gram_lp_point<KP, PREC>(bm, p0 + u, sh.ring.s, sh.ring.w, slot_c + u * NB * 256,
+                                  slot_b + u * KP);
+      }
+    }
+    // the slot's stores are complete before any lane reads them, and the
+    // ring's last reads before the eigensolve reuses its LDS
+    __threadfence_block();
+    wave_lds_sync();
+    // the lane's indices, redefined for every item: nothing derived from
+    // them may be hoisted out of the loop (that would keep the eigensolve's
+    // address arithmetic live through the Gram)
+    const int sg = opaque(seg), jl = opaque(jj);
+    const int pl = p0 + sg;
+    bool valid;
+    const EvdArgs e = evd_args_of(bm, pl, valid);
+    const int pv = valid ? pl : 0;
+    xf_body<KP>(e, valid, slot_c + sg * NB * 256, slot_b + sg * KP,
+                e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh.xf, sg, jl);
+    // the eigensolve's last reads of the slot and of LDS before the next
+    // item's Gram writes them
+    __threadfence_block();
+    wave_lds_sync();
+  });
+}
+
+template <int KP>
+hipError_t launch_fused_kp(const BatchMap& bm, int prec, hipStream_t s) {
+  if (bm.n <= 0) return hipSuccess;
+  if (launch_fill_i32(bm.queue, kQueueSlots, 0, s) != hipSuccess) return hipErrorLaunchFailure;
+  const int nitems = ceil_div(bm.n, 64 / KP);
+  const dim3 grid(nitems < kFusedBlocks ? nitems : kFusedBlocks), block(64);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_fused<KP, 0>), grid, block, 0, s, bm);
+  else if (prec == 1)
+    hipLaunchKernelGGL((k_fused<KP, 1>), grid, block, 0, s, bm);
+  else if (prec == 2)
+    hipLaunchKernelGGL((k_fused<KP, 2>), grid, block, 0, s, bm);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace letkf

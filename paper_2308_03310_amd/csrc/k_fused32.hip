@@ -1,0 +1,7 @@
+// The fused analysis kernels at KP = 32 (all precision forms).
+#define LETKF_OPAQUE_LANE 1
+#include "k_fused.h"
+
+namespace letkf {
+template hipError_t launch_fused_kp<32>(const BatchMap& bm, int prec, hipStream_t s);
+}  // namespace letkf

@@ -107,12 +107,10 @@ __device__ __forceinline__ int part_pos(int j) {
 // an entry below the diagonal block is read from its mirror), padded rows
 // unit, and this lane's entry of b.
 template <int KP>
-__device__ __forceinline__ void xf_load_row(const EvdArgs& e, int jj, int pl, bool valid,
+__device__ __forceinline__ void xf_load_row(const EvdArgs& e, const double* Cp, int jj, bool valid,
                                             double (&a)[KP]) {
   constexpr int NQ = KP / 16;
-  constexpr int NB = NQ * (NQ + 1) / 2;
   const bool real = valid && jj < e.k;
-  const double* Cp = e.C + (size_t)(valid ? pl : 0) * NB * 256;
   const int I = jj >> 4, r = jj & 15;
 #pragma unroll
   for (int J = 0; J < NQ; ++J) {
@@ -580,35 +578,33 @@ __device__ __forceinline__ bool xf_tridiagonal(double (&R)[kXfUp], double dj, do
 
 // Eigensolve, transform and in-place update of the point-major ensemble for
 // 64 / KP points per wavefront (mode 0 of EvdArgs).
+// The eigensolve, transform and update of one point on KP lanes (segment
+// seg of the wavefront): e its problem's descriptor, Cp its Gram output (the
+// upper blocks of C, then scratch for the Householder vectors), bp its b, xp
+// its ensemble row ([9][k], updated in place).  valid false: the segment
+// computes on padding and writes nothing.
 template <int KP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_evd_xf(BatchMap bm) {
-  constexpr int G = 64 / KP;
+__device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, double* Cp, const double* bp,
+                                        double* xp, XfLds<KP>& sh, int seg, int jj) {
   constexpr int NP = KP / 16;
-  __shared__ XfLds<KP> sh;
-  const int lane = lane_id();
-  const int seg = lane / KP, jj = lane % KP;
-  const int pl = blockIdx.x * G + seg;
-  bool valid;
-  const EvdArgs e = evd_args_of(bm, pl, valid);
   const int k = e.k;
 
   double a[KP];
-  xf_load_row<KP>(e, jj, pl, valid, a);
+  xf_load_row<KP>(e, Cp, jj, valid, a);
   double dj, ej;
   tridiagonalize<KP, kXfStream<KP>>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
   // the reflectors' global copy (when the registers cannot keep them through
   // the divide and conquer): this point's consumed Gram output
-  double* rv = e.C + (size_t)(valid ? pl : 0) * ((KP / 16) * (KP / 16 + 1) / 2) * 256;
+  double* rv = Cp;
   if constexpr (!kXfReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
 
   // rows of X: dX (nine components, ensemble mean removed) and b, row-part layout
   const int q = jj >> 4, c = jj & 15;
-  double* xp = e.xt + (size_t)(e.pt0 + (valid ? pl : 0)) * 9 * k;
   double x[16];
   {
     // row c < 9: component c of the point's members; row 9: b; one load per
     // entry, clamped to the row (entries past k and rows past 9 are zero)
-    const double* src = c < 9 ? xp + c * k : e.b + (size_t)(valid ? pl : 0) * KP;
+    const double* src = c < 9 ? xp + c * k : bp;
     const int jmax = c < 9 ? k - 1 : KP - 1;
     const bool row_ok = valid && c < kXfRows;
 #pragma unroll
@@ -680,6 +676,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
   }
   if (!finite) atomicOr(e.status, kStatNonfinite);
+}
+
+template <int KP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_evd_xf(BatchMap bm) {
+  constexpr int G = 64 / KP;
+  __shared__ XfLds<KP> sh;
+  const int lane = lane_id();
+  const int seg = lane / KP, jj = lane % KP;
+  const int pl = blockIdx.x * G + seg;
+  bool valid;
+  const EvdArgs e = evd_args_of(bm, pl, valid);
+  const int pv = valid ? pl : 0;
+  xf_body<KP>(e, valid, gram_c(bm, pv, KP), gram_b(bm, pv, KP),
+              e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh, seg, jj);
 }
 
 template <int KP>

@@ -115,21 +115,38 @@ inline int persistent_blocks(int n, int per_block) {
   return need < full ? need : full;
 }
 
+// Items [0, n) handed to the launch's wavefronts through the queues: f(item)
+// once per item, each on one wavefront (wave-uniform).
 template <class F>
-__device__ __forceinline__ void for_each_queued_point(const BatchMap& bm, F&& f) {
+__device__ __forceinline__ void for_each_queued(int* queue, int n, F&& f) {
   const int home = blockIdx.x & (kQueueSlots - 1);
   for (int qi = 0; qi < kQueueSlots; ++qi) {
     const int q = (home + qi) & (kQueueSlots - 1);
-    const int lo = (int)((int64_t)bm.n * q / kQueueSlots);
-    const int hi = (int)((int64_t)bm.n * (q + 1) / kQueueSlots);
+    const int lo = (int)((int64_t)n * q / kQueueSlots);
+    const int hi = (int)((int64_t)n * (q + 1) / kQueueSlots);
     for (;;) {
       int off = 0;
-      if (__lane_id() == 0) off = atomicAdd(bm.queue + q, 1);
+      if (__lane_id() == 0) off = atomicAdd(queue + q, 1);
       off = __builtin_amdgcn_readfirstlane(off);
       if (lo + off >= hi) break;             // wave-uniform exit
       f(lo + off);
     }
   }
+}
+
+template <class F>
+__device__ __forceinline__ void for_each_queued_point(const BatchMap& bm, F&& f) {
+  for_each_queued(bm.queue, bm.n, f);
+}
+
+// Slab-local point pl's Gram outputs: its NB upper 16 x 16 blocks of C and
+// its KP entries of b (KP = 16, 32 or 64).
+__device__ __forceinline__ double* gram_c(const BatchMap& bm, int pl, int kp) {
+  const int nq = kp / 16;
+  return bm.C + (size_t)pl * (nq * (nq + 1) / 2) * 256;
+}
+__device__ __forceinline__ double* gram_b(const BatchMap& bm, int pl, int kp) {
+  return bm.b + (size_t)pl * kp;
 }
 
 __device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gidx) {
@@ -174,6 +191,18 @@ hipError_t launch_evd_xf_kp(const BatchMap& bm, hipStream_t s);
 hipError_t launch_nsqrt(const double* a, int batch, int k, double* x, int* status, int* steps,
                         hipStream_t s);
 hipError_t launch_nsqrt_xf(const BatchMap& bm, int kp, hipStream_t s);
+// The fused form: Gram, eigensolve, transform and update of every point of
+// bm (g0 = 0, n = all points of its problems) in one persistent launch whose
+// blocks keep each point's C and b in their own slot of bm.C / bm.b
+// (fused_slot_c / fused_slot_b doubles per block).
+constexpr int kFusedBlocks = kDeviceCus * 8;
+template <int KP>
+hipError_t launch_fused_kp(const BatchMap& bm, int prec, hipStream_t s);
+// C and b doubles of one block's slot in the fused form (64 / kp points).
+__host__ __device__ constexpr uint64_t fused_slot_c(int kp) {
+  return (uint64_t)(64 / kp) * ((kp / 16) * (kp / 16 + 1) / 2) * 256;
+}
+__host__ __device__ constexpr uint64_t fused_slot_b(int kp) { return (uint64_t)(64 / kp) * kp; }
 hipError_t launch_bgk(const double* fin, double* fout, int k, int nx, int ny, double tau, double amp,
                       int force_kx, hipStream_t s);
 

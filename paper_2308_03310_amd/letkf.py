@@ -34,7 +34,8 @@ LETKF_FLAG_OBS_ON_HOST = 4
 LETKF_FLAG_DETERMINISTIC = 8
 LETKF_FLAG_GRAPH_CAPTURE = 16
 LETKF_FLAG_NSQRT = 32
-PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose")
+LETKF_FORM_GRID, LETKF_FORM_PERSISTENT, LETKF_FORM_FUSED, LETKF_FORM_AUTO = 0, 1, 2, 3
+PHASES = ("bin", "transpose", "obs_operator", "gram", "evd_update", "untranspose", "fused")
 
 
 class letkf_problem(ctypes.Structure):
@@ -57,7 +58,7 @@ class letkf_io(ctypes.Structure):
 
 
 class letkf_tuning(ctypes.Structure):
-    _fields_ = [("cell", ctypes.c_int32), ("gram_persistent", ctypes.c_int32),
+    _fields_ = [("cell", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("ms_per_call", ctypes.c_double)]
 
 
@@ -364,9 +365,10 @@ def letkf_tune(plan: int, ios: Iterable[letkf_io], stream=None) -> dict:
     t = letkf_tuning()
     _check(load_library().letkf_tune(plan, arr, len(ios), _stream(stream), ctypes.byref(t)),
            "letkf_tune")
-    return {"cell": t.cell, "gram_persistent": t.gram_persistent, "ms_per_call": t.ms_per_call}
+    return {"cell": t.cell, "form": t.form, "ms_per_call": t.ms_per_call}
 
 
-def letkf_set_tuning(plan: int, cell: int, gram_persistent: int) -> int:
-    t = letkf_tuning(int(cell), int(gram_persistent), 0.0)
+def letkf_set_tuning(plan: int, cell: int, form: int) -> int:
+    """Apply a setting: observation-cell edge and kernel form (LETKF_FORM_*)."""
+    t = letkf_tuning(int(cell), int(form), 0.0)
     return _check(load_library().letkf_set_tuning(plan, ctypes.byref(t)), "letkf_set_tuning")

@@ -105,16 +105,18 @@ def test_tuning_settings_and_autotuner(small_batch):
     plan = L.letkf_plan(probs)
     try:
         res = {}
+        forms = (L.LETKF_FORM_GRID, L.LETKF_FORM_PERSISTENT, L.LETKF_FORM_FUSED)
         for cell in (4, 8, 16):
-            for pers in (0, 1):
-                print(f"setting cell {cell}, persistent {pers}", flush=True)
-                L.letkf_set_tuning(plan, cell, pers)
+            for form in forms:
+                print(f"setting cell {cell}, form {form}", flush=True)
+                L.letkf_set_tuning(plan, cell, form)
                 L.letkf_analyze(plan, ios)
                 assert L.letkf_status(plan) == L.LETKF_OK
-                res[(cell, pers)] = _outputs(items)
+                res[(cell, form)] = _outputs(items)
         for cell in (4, 8, 16):
-            for i in range(len(items)):                  # same points, same order: same bits
-                assert np.array_equal(res[(cell, 0)][i], res[(cell, 1)][i]), (cell, i)
+            for form in forms[1:]:
+                for i in range(len(items)):              # same points, same order: same bits
+                    assert np.array_equal(res[(cell, 0)][i], res[(cell, form)][i]), (cell, form, i)
         for cell in (4, 16):                             # other summation order only
             for i in range(len(items)):
                 a, b = res[(cell, 0)][i], res[(8, 0)][i]
@@ -122,12 +124,14 @@ def test_tuning_settings_and_autotuner(small_batch):
         print("autotuner", flush=True)
         t = L.letkf_tune(plan, ios)
         print(f"  chose {t}", flush=True)
-        assert t["cell"] in (4, 8, 16) and t["gram_persistent"] in (0, 1) and t["ms_per_call"] > 0
+        assert t["cell"] in (4, 8, 16) and t["form"] in forms and t["ms_per_call"] > 0
         tuned = _outputs(items)
         for i in range(len(items)):
-            assert np.array_equal(tuned[i], res[(t["cell"], t["gram_persistent"])][i]), i
+            assert np.array_equal(tuned[i], res[(t["cell"], t["form"])][i]), i
         assert L.letkf_status(plan) == L.LETKF_OK
         with pytest.raises(L.LetkfError):
             L.letkf_set_tuning(plan, 12, 0)
+        with pytest.raises(L.LetkfError):
+            L.letkf_set_tuning(plan, 8, 4)
     finally:
         L.letkf_plan_destroy(plan)

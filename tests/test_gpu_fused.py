@@ -1,0 +1,157 @@
+"""The fused kernel form (LETKF_FORM_FUSED: Gram, eigensolve, transform and
+update of every point in one persistent launch) against the split forms:
+the arithmetic is the same code in the same order, so the analyses must be
+equal bit for bit -- on whole fields of the small and ragged workloads in
+every precision form, on a 512 x 512, k = 64 field (many items per
+wavefront of the persistent launch), with an invalid observation (the call
+is abandoned and the output left untouched), and in the phase record.  The
+split forms themselves are held to the oracle by the parity tests."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2308_03310_amd import synth
+from paper_2308_03310_amd import letkf as L
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _obs(p, torch):
+    f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+    return (f(p.obs_ix, torch.int32), f(p.obs_iy, torch.int32), f(p.obs_kind, torch.int32),
+            f(p.obs_val, torch.float64), f(p.obs_var, torch.float64))
+
+
+def _run(p, form, precision=L.LETKF_PREC_FP64, loc=L.LETKF_LOC_GAUSS, obs=None, fill=None,
+         flags=0):
+    import torch
+    wl = p.wl
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl, loc,
+                                        precision=precision)], flags=flags)
+    try:
+        L.letkf_set_tuning(plan, 8, form)
+        xb = torch.from_numpy(p.xb).cuda()
+        xa = torch.full_like(xb, fill) if fill is not None else torch.empty_like(xb)
+        obs = obs if obs is not None else _obs(p, torch)     # alive until the sync below
+        L.letkf_analyze(plan, [L.make_io(0, xb, xa, obs)])
+        st = L.letkf_status(plan, sync=True)
+        return xa.cpu().numpy(), st
+    finally:
+        L.letkf_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("precision", [L.LETKF_PREC_FP64, L.LETKF_PREC_FP32, L.LETKF_PREC_BF16])
+def test_fused_equals_grid_cpu32(device, precision):
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say(f"cpu32_k16 precision {precision}: grid vs fused")
+    a, sa = _run(p, L.LETKF_FORM_GRID, precision)
+    b, sb = _run(p, L.LETKF_FORM_FUSED, precision)
+    assert sa == sb == L.LETKF_OK
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("k", [5, 20, 40, 64])
+@pytest.mark.parametrize("loc", [L.LETKF_LOC_GAUSS, L.LETKF_LOC_NONE])
+def test_fused_equals_grid_ragged(device, k, loc):
+    # 40 x 27 points: the last item of four (k <= 16) or two (k <= 32) points
+    # is partly padding
+    wl = synth.Workload("ragged", 40, 27, k, 3, 0.01, 3.3, 1.15, 40 + k,
+                        kinds=(synth.OBS_RHO, synth.OBS_U, synth.OBS_V))
+    p = synth.make_problem(wl)
+    say(f"ragged 40x27 k={k} loc={loc}: grid vs persistent vs fused")
+    a, sa = _run(p, L.LETKF_FORM_GRID, loc=loc)
+    b, sb = _run(p, L.LETKF_FORM_PERSISTENT, loc=loc)
+    c, sc = _run(p, L.LETKF_FORM_FUSED, loc=loc)
+    assert sa == sb == sc == L.LETKF_OK
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_fused_equals_grid_512_k64(device):
+    wl = synth.Workload("grid512_k64", 512, 512, 64, 4, 0.005, 12.0, 1.1, 5)
+    say("generate 512x512 k=64")
+    p = synth.make_problem(wl)
+    say("512x512 k=64 FP32 form: grid vs fused")
+    a, sa = _run(p, L.LETKF_FORM_GRID, L.LETKF_PREC_FP32)
+    b, sb = _run(p, L.LETKF_FORM_FUSED, L.LETKF_PREC_FP32)
+    assert sa == sb == L.LETKF_OK
+    assert np.isfinite(b).all()
+    assert np.array_equal(a, b)
+
+
+def test_fused_invalid_observation_leaves_output(device):
+    import torch
+    p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
+    say("fused form with an invalid observation variance")
+    obs = list(_obs(p, torch))
+    obs[4] = obs[4].clone()
+    obs[4][5] = -1.0
+    got, st = _run(p, L.LETKF_FORM_FUSED, obs=tuple(obs), fill=-7.0)
+    assert st == L.LETKF_EINVAL
+    assert np.all(got == -7.0)
+
+
+def test_auto_form_phase_record_mixed_widths(device):
+    """AUTO: the k = 64 problem of a batched call runs fused, the k = 16 one
+    split; the phase record counts one fused launch and the split pairs, and
+    the outputs equal the grid form's."""
+    import torch
+    wls = [synth.Workload("a64", 48, 40, 64, 3, 0.01, 3.0, 1.1, 11),
+           synth.Workload("a16", 40, 36, 16, 2, 0.01, 4.0, 1.1, 12)]
+    ps = [synth.make_problem(w) for w in wls]
+    probs = [L.make_problem(w.nx, w.ny, w.k, len(p.obs_ix), w.L, w.infl) for w, p in zip(wls, ps)]
+    outs = {}
+    for form in (L.LETKF_FORM_GRID, L.LETKF_FORM_AUTO):
+        say(f"mixed widths, form {form}")
+        plan = L.letkf_plan(probs, flags=L.LETKF_FLAG_PHASE_TIMING)
+        try:
+            L.letkf_set_tuning(plan, 8, form)
+            keep, ios = [], []
+            for i, p in enumerate(ps):
+                xb = torch.from_numpy(p.xb).cuda()
+                xa = torch.empty_like(xb)
+                obs = _obs(p, torch)              # kept alive until the call has run
+                keep.append((xb, xa, obs))
+                ios.append(L.make_io(i, xb, xa, obs))
+            L.letkf_analyze(plan, ios)
+            calls, ms, launches = L.letkf_phase_times(plan)
+            assert L.letkf_status(plan, sync=True) == L.LETKF_OK
+            outs[form] = [xa.cpu().numpy() for _, xa, _ in keep]
+            if form == L.LETKF_FORM_AUTO:
+                assert launches["fused"] == 1 and launches["gram"] == launches["evd_update"] >= 1
+                assert ms["fused"] > 0.0 and ms["gram"] > 0.0
+            else:
+                assert launches["fused"] == 0
+        finally:
+            L.letkf_plan_destroy(plan)
+    for a, b in zip(outs[L.LETKF_FORM_GRID], outs[L.LETKF_FORM_AUTO]):
+        assert np.array_equal(a, b)
+
+
+def test_fused_phase_record(device):
+    import torch
+    wl = synth.WORKLOADS["cpu32_k16"]
+    p = synth.make_problem(wl)
+    say("fused form phase times")
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl)],
+                        flags=L.LETKF_FLAG_PHASE_TIMING)
+    try:
+        L.letkf_set_tuning(plan, 8, L.LETKF_FORM_FUSED)
+        xb = torch.from_numpy(p.xb).cuda()
+        xa = torch.empty_like(xb)
+        obs = _obs(p, torch)
+        for _ in range(3):
+            L.letkf_analyze(plan, [L.make_io(0, xb, xa, obs)])
+        calls, ms, launches = L.letkf_phase_times(plan)
+        assert calls == 3
+        assert launches["fused"] == 1 and launches["gram"] == 0 and launches["evd_update"] == 0
+        assert ms["fused"] > 0.0 and ms["gram"] == 0.0 and ms["evd_update"] == 0.0
+        assert L.letkf_status(plan) == L.LETKF_OK
+    finally:
+        L.letkf_plan_destroy(plan)

@@ -114,7 +114,7 @@ def test_tune_cache_roundtrip(device, tmp_path):
     finally:
         L.letkf_plan_destroy(plan)
     line = open(path).read().split()
-    assert len(line) == 4 and int(line[1]) == t["cell"] and int(line[2]) == t["gram_persistent"]
+    assert len(line) == 4 and int(line[1]) == t["cell"] and int(line[2]) == t["form"]
     print(f"  chose {t}; a new plan loads it", flush=True)
     plan = _mk(p, tune_cache_path=path)
     try:
@@ -163,12 +163,14 @@ def test_deterministic_tune_keeps_cell(device, tmp_path):
         L.letkf_plan_destroy(plan)
 
 
-def test_graph_capture_plan_replays(device):
+@pytest.mark.parametrize("form", [L.LETKF_FORM_GRID, L.LETKF_FORM_FUSED])
+def test_graph_capture_plan_replays(device, form):
     import torch
     p = _problem()
     obs = _obs(p, torch)
     plan = _mk(p, flags=L.LETKF_FLAG_GRAPH_CAPTURE)
     try:
+        L.letkf_set_tuning(plan, 8, form)
         xb = _dev(p.xb, torch.float64)
         xa = torch.empty_like(xb)
         io = [L.make_io(0, xb, xa, obs)]
