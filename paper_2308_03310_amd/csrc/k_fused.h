@@ -4,15 +4,17 @@
 //
 // Each block is one wavefront that takes items of 64 / KP consecutive points
 // from the per-XCD work queues (neighbouring points share observations, so an
-// XCD's L2 keeps serving them), forms the items' C and b one point after
-// another into its own slot of global memory, then runs the eigensolve and
-// update on the item, one point per KP lanes.  The slot is written and read
-// back by the same wavefront right away, so C stays in the L2 instead of
-// making the round trip through HBM that separate Gram and eigensolve
-// launches need, and the whole analysis is one launch of device-filling
-// size instead of two launches per slab.  The Gram's gathers and the FP64
-// eigensolve of the other wavefronts on a SIMD overlap.  The arithmetic is
-// that of the separate kernels, so results are bitwise the same.
+// XCD's L2 keeps serving them), forms the items' C one point after another
+// as packed upper triangles in LDS (16.6 KB at KP = 64, within the
+// eigensolve's own LDS, which it shares) and b in its own slot of global
+// memory, then runs the eigensolve and update on the item, one point per KP
+// lanes.  C thus never leaves the CU (separate Gram and eigensolve launches
+// send it through HBM and back); at KP = 64 the Householder vectors still
+// wait in the block's slot through the divide and conquer, as in the
+// separate kernel.  The whole analysis is one launch of device-filling size
+// instead of two launches per slab, and the Gram's gathers overlap the FP64
+// eigensolve of the other wavefronts on a SIMD.  The arithmetic is that of
+// the separate kernels, so results are bitwise the same.
 #pragma once
 #include "common.h"
 #include "launch.h"
@@ -24,11 +26,14 @@ namespace letkf {
 
 template <int KP>
 struct FusedLds {
+  static constexpr int G = 64 / KP;
+  static constexpr int NPK = KP * (KP + 1) / 2;   // packed upper triangle
   union {
-    struct {                      // the Gram's ring of local observations
-      int s[kRing];
+    struct {                      // the Gram: its ring of local observations and
+      int s[kRing];               // the item's C matrices
       double w[kRing];
-    } ring;
+      double c[G][NPK];
+    } gram;
     XfLds<KP> xf;
   };
 };
@@ -49,15 +54,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int u = 0; u < G; ++u) {
       if (p0 + u < bm.n) {                     // uniform
         if constexpr (PREC == 0)
-          gram_f64_point<KP>(bm, p0 + u, sh.ring.s, sh.ring.w, slot_c + u * NB * 256,
-                             slot_b + u * KP);
+          gram_f64_point<KP, true>(bm, p0 + u, sh.gram.s, sh.gram.w, sh.gram.c[u],
+                                   slot_b + u * KP);
         else
-          gram_lp_point<KP, PREC>(bm, p0 + u, sh.ring.s, sh.ring.w, slot_c + u * NB * 256,
-                                  slot_b + u * KP);
+          gram_lp_point<KP, PREC, true>(bm, p0 + u, sh.gram.s, sh.gram.w, sh.gram.c[u],
+                                        slot_b + u * KP);
       }
     }
-    // the slot's stores are complete before any lane reads them, and the
-    // ring's last reads before the eigensolve reuses its LDS
+    // b's stores are complete before any lane reads them, and C's LDS
+    // stores are visible to every lane
     __threadfence_block();
     wave_lds_sync();
     // the lane's indices, redefined for every item: nothing derived from
@@ -68,8 +73,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     bool valid;
     const EvdArgs e = evd_args_of(bm, pl, valid);
     const int pv = valid ? pl : 0;
-    xf_body<KP>(e, valid, slot_c + sg * NB * 256, slot_b + sg * KP,
-                e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh.xf, sg, jl);
+    xf_body<KP, true>(e, valid, sh.gram.c[sg], slot_c + sg * NB * 256, slot_b + sg * KP,
+                      e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh.xf, sg, jl);
     // the eigensolve's last reads of the slot and of LDS before the next
     // item's Gram writes them
     __threadfence_block();

@@ -120,11 +120,12 @@ __device__ __forceinline__ void gram_drain(GramAcc<KQ>& acc, const GramArgs& g, 
 }
 
 // The localized Gram matrix and right-hand side of slab-local point pl, by
-// one wavefront, into Cp (the point's NB upper blocks of 256) and bp (KQ
-// entries); ring_s / ring_w are its LDS ring of local observations.
+// one wavefront, into Cp (the point's NB upper blocks of 256, or with PACKED
+// its packed upper triangle) and bp (KQ entries); ring_s / ring_w are its LDS
+// ring of local observations.
 // The loads of each candidate batch are issued before the ring filled by the
 // previous batch is drained.
-template <int KQ>
+template <int KQ, bool PACKED = false>
 __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* ring_s,
                                                double* ring_w, double* Cp, double* bp) {
   constexpr int NQ = KQ / 16;
@@ -188,11 +189,8 @@ __device__ __forceinline__ void gram_f64_point(const BatchMap& bm, int pl, int* 
   // C blocks: the f64 16x16x4 accumulator gives lane l, element r the entry
   // (row 4*r + l/16, column l%16) of each block.
   const int e = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Cp[b * 256 + (4 * r + e) * 16 + col] = acc.c[b][r];
-  }
+  store_gram_blocks<KQ, PACKED>(
+      Cp, [&](int b, int r) { return acc.c[b][r]; }, [&](int r) { return 4 * r + e; }, col);
 }
 
 }  // namespace letkf

@@ -164,8 +164,9 @@ __device__ __forceinline__ void gram_drain_lp(GramAccLp<KQ, PREC>& acc, const Gr
 }
 
 // The point routine of k_gram_f64 (k_gram.h) in reduced precision: slab-local
-// point pl by one wavefront, into Cp (NB upper blocks) and bp (KQ entries).
-template <int KQ, int PREC>
+// point pl by one wavefront, into Cp (NB upper blocks, or with PACKED the
+// packed upper triangle) and bp (KQ entries).
+template <int KQ, int PREC, bool PACKED = false>
 __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* ring_s,
                                               double* ring_w, double* Cp, double* bp) {
   constexpr int NQ = KQ / 16;
@@ -225,11 +226,9 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
     if (lane < 16) bp[16 * I + lane] = v;
   }
   const int col = lane & 15;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Cp[b * 256 + f32_acc_row(lane, r) * 16 + col] = (double)acc.c[b][r];
-  }
+  store_gram_blocks<KQ, PACKED>(
+      Cp, [&](int b, int r) { return (double)acc.c[b][r]; },
+      [&](int r) { return f32_acc_row(lane, r); }, col);
 }
 
 }  // namespace letkf

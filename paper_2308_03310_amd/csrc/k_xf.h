@@ -114,22 +114,42 @@ __device__ __forceinline__ void xf_load_row(const EvdArgs& e, const double* Cp, 
   const int I = jj >> 4, r = jj & 15;
 #pragma unroll
   for (int J = 0; J < NQ; ++J) {
-    // block (min(I,J), max(I,J)) in row-major upper order
+    // block (min(I,J), max(I,J)) in row-major upper order; only the upper
+    // triangle of C is read (its diagonal blocks' two triangles differ by
+    // rounding), so the row is that of an exactly symmetric matrix, as the
+    // packed form gives it
     const int lo = I < J ? I : J, hi = I < J ? J : I;
     const int blk = lo * NQ - lo * (lo - 1) / 2 + (hi - lo);
     const double* B = Cp + blk * 256;
-    if (J >= I) {
+    if (J > I) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[16 * J + c] = ldg(B, r * 16 + c);
-    } else {
+    } else if (J < I) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[16 * J + c] = ldg(B, c * 16 + r);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[16 * J + c] = ldg(B, c >= r ? r * 16 + c : c * 16 + r);
     }
   }
 #pragma unroll
   for (int c = 0; c < KP; ++c) {
     const double v = real ? a[c] : 0.0;
     a[c] = c == jj ? (real ? v + e.alpha : 1.0) : v;
+  }
+}
+
+// Row jj of Q from C held as its packed upper triangle in LDS (the fused
+// kernel), as xf_load_row.
+template <int KP>
+__device__ __forceinline__ void xf_load_row_packed(const EvdArgs& e, const double* Cq, int jj,
+                                                   bool valid, double (&a)[KP]) {
+  const bool real = valid && jj < e.k;
+  const auto* lds = (const __attribute__((address_space(3))) double*)Cq;
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    const double v = c >= jj ? lds[packed_upper(jj, c, KP)] : lds[packed_upper(c, jj, KP)];
+    a[c] = c == jj ? (real ? v + e.alpha : 1.0) : (real ? v : 0.0);
   }
 }
 
@@ -579,23 +599,29 @@ __device__ __forceinline__ bool xf_tridiagonal(double (&R)[kXfUp], double dj, do
 // Eigensolve, transform and in-place update of the point-major ensemble for
 // 64 / KP points per wavefront (mode 0 of EvdArgs).
 // The eigensolve, transform and update of one point on KP lanes (segment
-// seg of the wavefront): e its problem's descriptor, Cp its Gram output (the
-// upper blocks of C, then scratch for the Householder vectors), bp its b, xp
-// its ensemble row ([9][k], updated in place).  valid false: the segment
-// computes on padding and writes nothing.
-template <int KP>
-__device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, double* Cp, const double* bp,
-                                        double* xp, XfLds<KP>& sh, int seg, int jj) {
+// seg of the wavefront): e its problem's descriptor, Cq its Gram output (the
+// upper 16 x 16 blocks of C in global memory, or with PACKED the packed upper
+// triangle in LDS, consumed before the eigensolve uses its LDS), rv global
+// scratch for the Householder vectors (k (k - 1) / 2 doubles, used when the
+// registers cannot keep them), bp its b, xp its ensemble row ([9][k],
+// updated in place).  valid false: the segment computes on padding and
+// writes nothing.
+template <int KP, bool PACKED = false>
+__device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const double* Cq, double* rv,
+                                        const double* bp, double* xp, XfLds<KP>& sh, int seg,
+                                        int jj) {
   constexpr int NP = KP / 16;
   const int k = e.k;
 
   double a[KP];
-  xf_load_row<KP>(e, Cp, jj, valid, a);
+  if constexpr (PACKED) {
+    xf_load_row_packed<KP>(e, Cq, jj, valid, a);
+    wave_lds_sync();                 // C is read before the reduction's LDS use
+  } else {
+    xf_load_row<KP>(e, Cq, jj, valid, a);
+  }
   double dj, ej;
   tridiagonalize<KP, kXfStream<KP>>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
-  // the reflectors' global copy (when the registers cannot keep them through
-  // the divide and conquer): this point's consumed Gram output
-  double* rv = Cp;
   if constexpr (!kXfReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
 
   // rows of X: dX (nine components, ensemble mean removed) and b, row-part layout
@@ -688,8 +714,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   bool valid;
   const EvdArgs e = evd_args_of(bm, pl, valid);
   const int pv = valid ? pl : 0;
-  xf_body<KP>(e, valid, gram_c(bm, pv, KP), gram_b(bm, pv, KP),
-              e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh, seg, jj);
+  // the reflectors' global copy goes to the point's consumed Gram output
+  double* cp = gram_c(bm, pv, KP);
+  xf_body<KP>(e, valid, cp, cp, gram_b(bm, pv, KP), e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh,
+              seg, jj);
 }
 
 template <int KP>

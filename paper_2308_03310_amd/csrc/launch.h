@@ -149,6 +149,40 @@ __device__ __forceinline__ double* gram_b(const BatchMap& bm, int pl, int kp) {
   return bm.b + (size_t)pl * kp;
 }
 
+// Position of entry (i, j), i <= j, of a KP x KP symmetric matrix stored as
+// its packed upper triangle, row by row.
+__host__ __device__ constexpr int packed_upper(int i, int j, int kp) {
+  return i * kp - i * (i - 1) / 2 + (j - i);
+}
+
+// Writes the upper 16 x 16 blocks of a Gram matrix from MFMA accumulators:
+// acc(b, r) is element r of block b's accumulator (blocks (I, J), I <= J, in
+// row-major order), holding entry (row(r), col) of the block.  PACKED false:
+// the blocks as they are, 256 entries each (global memory); PACKED true: the
+// packed upper triangle of the KP x KP matrix (the fused kernel's LDS).
+template <int KP, bool PACKED, class Acc, class Row>
+__device__ __forceinline__ void store_gram_blocks(double* Cp, Acc acc, Row row, int col) {
+  constexpr int NQ = KP / 16;
+  int b = 0;
+#pragma unroll
+  for (int I = 0; I < NQ; ++I) {
+#pragma unroll
+    for (int J = I; J < NQ; ++J, ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = row(r);
+        if constexpr (PACKED) {
+          const int i = 16 * I + rr, j = 16 * J + col;
+          auto* lds = (__attribute__((address_space(3))) double*)Cp;
+          if (I < J || rr <= col) lds[packed_upper(i, j, KP)] = acc(b, r);
+        } else {
+          Cp[b * 256 + rr * 16 + col] = acc(b, r);
+        }
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ int find_problem(const int* prefix, int nprob, int gidx) {
   int lo = 0, hi = nprob;
   while (hi - lo > 1) {
