@@ -5,7 +5,8 @@
 // mean subtraction) and the weighted operand w_j dy_j in FP32 or BF16, and
 // FP32 accumulation on MFMA:
 //   FP32: v_mfma_f32_16x16x4f32      (4 local observations per K-step)
-//   BF16: v_mfma_f32_16x16x16bf16_1k (16 local observations per K-step)
+//   BF16: v_mfma_f32_16x16x32_bf16   (32 local observations per K-step, the
+//         double-K form of gfx950)
 // C and b are written as FP64 for the FP64 eigensolve.
 #pragma once
 #include <type_traits>
@@ -16,7 +17,14 @@
 
 namespace letkf {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// Ring entries per lane and step: FP32 1 (K = 4 over the four 16-lane
+// groups), BF16 8 (K = 32).
+template <int PREC>
+constexpr int lp_entries() {
+  return PREC == 1 ? 1 : 8;
+}
 
 // Accumulator element r of lane l of a 16x16 f32 MFMA block holds row
 // f32_acc_row(l, r), column l % 16.
@@ -31,7 +39,7 @@ struct GramAccLp {
 };
 
 // Ring entries of one step: R per lane (FP32: entry head + lane / 16; BF16:
-// entries head + 4 (lane / 16) + t, t < 4).  Every ring slot holds a valid
+// entries head + 8 (lane / 16) + t, t < 8).  Every ring slot holds a valid
 // observation index and a finite weight (cleared when a point starts), so
 // the reads need no branch; entries past the tail get weight 0.
 template <int R>
@@ -104,20 +112,22 @@ __device__ __forceinline__ void gram_accumulate_lp(GramAccLp<KQ, 1>& acc,
   }
 }
 
-// BF16: four entries per 16-lane group, K = 16; the weighted operand is
+// BF16: eight entries per 16-lane group, K = 32; the weighted operand is
 // rounded to BF16 and the right-hand side accumulates that rounded value.
+// A and B take the lane's entries in the same order, so the sum over K is
+// the same whatever order the instruction gives the eight.
 template <int KQ>
 __device__ __forceinline__ void gram_accumulate_lp(GramAccLp<KQ, 2>& acc,
-                                                   const GramStepLp<KQ, 4, unsigned short>& st) {
+                                                   const GramStepLp<KQ, 8, unsigned short>& st) {
   constexpr int NQ = KQ / 16;
-  short4_t A[NQ], B[NQ];
+  bf16x8_t A[NQ], B[NQ];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < 8; ++t) {
 #pragma unroll
     for (int I = 0; I < NQ; ++I) {
       const unsigned short ab = to_bf16(st.w[t] * from_bf16(st.y[t][I]));
-      A[I][t] = (short)ab;
-      B[I][t] = (short)st.y[t][I];
+      A[I][t] = __builtin_bit_cast(__bf16, ab);
+      B[I][t] = __builtin_bit_cast(__bf16, st.y[t][I]);
       acc.bacc[I] = fmaf(from_bf16(ab), st.dv[t], acc.bacc[I]);
     }
   }
@@ -126,7 +136,7 @@ __device__ __forceinline__ void gram_accumulate_lp(GramAccLp<KQ, 2>& acc,
   for (int I = 0; I < NQ; ++I) {
 #pragma unroll
     for (int J = I; J < NQ; ++J) {
-      acc.c[blk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[I], B[J], acc.c[blk], 0, 0, 0);
+      acc.c[blk] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[I], B[J], acc.c[blk], 0, 0, 0);
       ++blk;
     }
   }
@@ -138,7 +148,7 @@ template <int KQ, int PREC>
 __device__ __forceinline__ void gram_drain_lp(GramAccLp<KQ, PREC>& acc, const GramArgs& g,
                                               const int* ring_s, const double* ring_w, int& head,
                                               int tail) {
-  constexpr int R = PREC == 1 ? 1 : 4;
+  constexpr int R = lp_entries<PREC>();
   constexpr int STEP = 4 * R;
   typedef typename std::conditional<PREC == 1, float, unsigned short>::type E;
   const int n = (tail - head) / STEP;
@@ -171,7 +181,7 @@ __device__ __forceinline__ void gram_lp_point(const BatchMap& bm, int pl, int* r
                                               double* ring_w, double* Cp, double* bp) {
   constexpr int NQ = KQ / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
-  constexpr int R = PREC == 1 ? 1 : 4;
+  constexpr int R = lp_entries<PREC>();
   typedef typename std::conditional<PREC == 1, float, unsigned short>::type E;
   const int lane = lane_id();
   // the point is the wavefront's: uniform (scalar registers and loads)

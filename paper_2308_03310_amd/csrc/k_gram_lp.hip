@@ -6,7 +6,7 @@ namespace letkf {
 
 // Grid and persistent forms, as for k_gram_f64.
 template <int KQ, int PREC, bool PERSIST>
-__global__ __launch_bounds__(256) void k_gram_lp(BatchMap bm) {
+__global__ __launch_bounds__(256, 2) void k_gram_lp(BatchMap bm) {
   __shared__ int s_ring[4][kRing];
   __shared__ double w_ring[4][kRing];
   const int wid = threadIdx.x >> 6;
