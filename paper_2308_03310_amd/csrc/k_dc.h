@@ -550,6 +550,136 @@ __device__ __forceinline__ void dc_levels(double (&qs)[KP], double& lam, DcLds<K
   }
 }
 
+// ---- 4 x 4 leaves of the divide and conquer, one per quad of lanes ----
+// Lane t of a quad holds row t of the leaf A and row t of the accumulated
+// rotations V (A_0 = V diag(lam) V^T at the end).  Cyclic Jacobi (Golub &
+// Van Loan, Sec. 8.5) in the parallel order {(0,1),(2,3)}, {(0,2),(1,3)},
+// {(0,3),(1,2)}: the two rotations of a round act on disjoint index pairs,
+// so each lane applies both to its row's columns, then the rotation of its
+// own pair to the rows (with its partner's row).  Quad exchanges are DPP
+// quad permutations: 0xB1 lane ^ 1, 0x4E lane ^ 2, 0x1B lane ^ 3.
+
+__device__ __forceinline__ double sel4(const double (&x)[4], int t) {
+  return t == 0 ? x[0] : t == 1 ? x[1] : t == 2 ? x[2] : x[3];
+}
+
+// The symmetric Schur rotation of the 2 x 2 block (app, apq; apq, aqq):
+// c, s with J = [[c, s], [-s, c]] and J^T A J diagonal (as the 2 x 2 leaves).
+__device__ __forceinline__ void schur2(double app, double aqq, double apq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (apq != 0.0) {
+    const double th = (aqq - app) / (2.0 * apq);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    s = t * c;
+  }
+}
+
+// Columns p, q of a row rotated: (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q).
+template <int P, int Q>
+__device__ __forceinline__ void rot_cols(double (&x)[4], double c, double s) {
+  const double xp = x[P], xq = x[Q];
+  x[P] = fma(c, xp, -s * xq);
+  x[Q] = fma(s, xp, c * xq);
+}
+
+// One round: pairs (P0, Q0) and (P1, Q1); PART is the DPP pattern of the
+// partner in one's own pair, OTHER that of a lane of the other pair.
+template <int P0, int Q0, int P1, int Q1, int PART, int OTHER>
+__device__ __forceinline__ void jacobi4_round(double (&A)[4], double (&V)[4], int t) {
+  const bool first = t == P0 || t == Q0;
+  const int p = first ? P0 : P1, q = first ? Q0 : Q1;
+  const bool isp = t == p;
+  // the pair's entries: a_pp and a_qq from their lanes, a_pq from row p, so
+  // that both lanes of the pair compute the same rotation
+  const double d = sel4(A, t);
+  const double dp = dpp_lane<PART>(d);
+  const double o = sel4(A, q);                 // row p: a_pq (row q: unused)
+  const double op = dpp_lane<PART>(o);
+  double c, s;
+  schur2(isp ? d : dp, isp ? dp : d, isp ? o : op, c, s);
+  const double co = dpp_lane<OTHER>(c), so = dpp_lane<OTHER>(s);
+  const double c0 = first ? c : co, s0 = first ? s : so;
+  const double c1 = first ? co : c, s1 = first ? so : s;
+  // A <- A J, V <- V J
+  rot_cols<P0, Q0>(A, c0, s0);
+  rot_cols<P1, Q1>(A, c1, s1);
+  rot_cols<P0, Q0>(V, c0, s0);
+  rot_cols<P1, Q1>(V, c1, s1);
+  // A <- J^T A: row p <- c row_p - s row_q, row q <- s row_p + c row_q
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double other = dpp_lane<PART>(A[j]);
+    A[j] = isp ? fma(c, A[j], -s * other) : fma(s, other, c * A[j]);
+  }
+}
+
+// Sum over the quad.
+__device__ __forceinline__ double quad_sum(double x) {
+  x += dpp_lane<0xB1>(x);
+  return x + dpp_lane<0x4E>(x);
+}
+
+// x[t ^ M] of lane t ^ M, for each lane t (the quad's values of register t
+// transposed through lane pairs t, t ^ M).
+template <int M>
+__device__ __forceinline__ double quad_xchg(const double (&x)[4], int t) {
+  constexpr int CTRL = M == 1 ? 0xB1 : M == 2 ? 0x4E : 0x1B;
+  return dpp_lane<CTRL>(sel4(x, t ^ M));
+}
+
+// The leaf's eigendecomposition: lam = this lane's eigenvalue, Vc = column t
+// of V (V[0..3][t]: the eigenvector of lam), Vr = row t of V.  Sweeps until
+// every leaf of the wavefront is diagonal to 1e-15 of its norm (at most 8;
+// a 4 x 4 symmetric matrix takes 3 or 4 in FP64).
+__device__ __forceinline__ void jacobi4(double (&A)[4], double& lam, double (&Vc)[4],
+                                        double (&Vr)[4], int t) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Vr[j] = j == t ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 8; ++sweep) {
+    double off = 0.0, fro = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double a2 = A[j] * A[j];
+      fro += a2;
+      off += j == t ? 0.0 : a2;
+    }
+    off = quad_sum(off);
+    fro = quad_sum(fro);
+    if (__ballot(off > 1e-30 * fro) == 0) break;         // wave-uniform
+    jacobi4_round<0, 1, 2, 3, 0xB1, 0x4E>(A, Vr, t);
+    jacobi4_round<0, 2, 1, 3, 0x4E, 0xB1>(A, Vr, t);
+    jacobi4_round<0, 3, 1, 2, 0x1B, 0xB1>(A, Vr, t);
+  }
+  lam = sel4(A, t);
+  // column t of V: V[s][t] is lane s's entry t
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Vc[j] = 0.0;
+  const double own = sel4(Vr, t);
+  const double x1 = quad_xchg<1>(Vr, t), x2 = quad_xchg<2>(Vr, t), x3 = quad_xchg<3>(Vr, t);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int m = s ^ t;
+    Vc[s] = m == 0 ? own : m == 1 ? x1 : m == 2 ? x2 : x3;
+  }
+}
+
+// Row t = jj % 4 of the 4 x 4 leaf of T at lane jj (d_jj = dj, e_jj = ej =
+// T[jj+1][jj]): T torn at every fourth coupling (Cuppen: a torn coupling
+// comes off both diagonal entries it joins; e_{KP-1} = 0).
+template <int KP>
+__device__ __forceinline__ void leaf4(double dj, double ej, int jj, double (&A)[4]) {
+  const int t = jj & 3, a4 = jj & ~3;
+  const double eabove = __shfl(ej, a4 > 0 ? a4 - 1 : 0, KP);
+  const double eleft = dpp_lane<0x90>(ej);       // quad_perm [0,0,1,2]: lane t - 1's coupling
+  double dd = dj;
+  if (t == 0 && a4 > 0) dd -= eabove;
+  if (t == 3) dd -= ej;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) A[j] = j == t ? dd : (j == t + 1 ? ej : (j == t - 1 ? eleft : 0.0));
+}
+
 // Eigen-decomposition of the tridiagonal (d, e), lane jj of the KP-lane group
 // holding dj = d_jj and ej = e_jj = T[jj+1][jj] (e_{KP-1} = 0).  Deflation tolerance 8 deps max(|D|, rho) per merge, with
 // deps the unit roundoff of the arithmetic that produced the matrix.  On
@@ -559,32 +689,17 @@ template <int KP>
 __device__ __forceinline__ bool dc_tridiagonal(double (&qs)[KP], double& lam, DcLds<KP>& L,
                                                double dj, double ej, double* W, int jj,
                                                double deps) {
-  // Leaves of size 2: T torn at every other coupling, each 2 x 2 block
-  // [[d_a - e_{a-1}, e_a], [e_a, d_{a+1} - e_{a+1}]] diagonalized in closed
-  // form by one Jacobi rotation (Golub & Van Loan, sym.schur2): J^T A J =
-  // diag(A_00 - t e_a, A_11 + t e_a) with J = [[c, s], [-s, c]].
-  const int a = jj & ~1;
-  const double em1 = __shfl(ej, a > 0 ? a - 1 : 0, KP);
-  const double A0 = __shfl(dj, a, KP) - (a > 0 ? em1 : 0.0);
-  const double A1 = __shfl(dj, a + 1, KP) - __shfl(ej, a + 1, KP);
-  const double b = __shfl(ej, a, KP);
-  double c = 1.0, sn = 0.0, l0 = A0, l1 = A1;
-  if (b != 0.0) {
-    const double th = (A1 - A0) / (2.0 * b);
-    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-    c = 1.0 / sqrt(fma(t, t, 1.0));
-    sn = t * c;
-    l0 = fma(-t, b, A0);
-    l1 = fma(t, b, A1);
-  }
-  const bool top = jj == a;                  // row a: (c, s); row a + 1: (-s, c)
-  lam = top ? l0 : l1;                       // column 0 <-> l0, column 1 <-> l1
+  // 4 x 4 leaves (leaf4), each diagonalized by Jacobi on its quad of lanes;
+  // row t of the leaf's eigenvector matrix is the row restricted to the
+  // leaf's columns
+  const int t = jj & 3;
+  double A[4], Vc[4], Vr[4];
+  leaf4<KP>(dj, ej, jj, A);
+  jacobi4(A, lam, Vc, Vr, t);
 #pragma unroll
-  for (int q = 0; q < KP; ++q) qs[q] = 0.0;
-  qs[0] = top ? c : -sn;
-  qs[1] = top ? sn : c;
+  for (int q = 0; q < KP; ++q) qs[q] = q < 4 ? Vr[q] : 0.0;
   bool ok = true;
-  dc_levels<KP, 4>(qs, lam, L, ej, W, jj, deps, ok);
+  dc_levels<KP, 8>(qs, lam, L, ej, W, jj, deps, ok);
   return ok;
 }
 

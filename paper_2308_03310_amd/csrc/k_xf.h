@@ -550,121 +550,6 @@ __device__ __forceinline__ void xf_levels(double (&R)[kXfUp], double lam, double
   }
 }
 
-// ---- 4 x 4 leaves of the divide and conquer, one per quad of lanes ----
-// Lane t of a quad holds row t of the leaf A and row t of the accumulated
-// rotations V (A_0 = V diag(lam) V^T at the end).  Cyclic Jacobi (Golub &
-// Van Loan, Sec. 8.5) in the parallel order {(0,1),(2,3)}, {(0,2),(1,3)},
-// {(0,3),(1,2)}: the two rotations of a round act on disjoint index pairs,
-// so each lane applies both to its row's columns, then the rotation of its
-// own pair to the rows (with its partner's row).  Quad exchanges are DPP
-// quad permutations: 0xB1 lane ^ 1, 0x4E lane ^ 2, 0x1B lane ^ 3.
-
-__device__ __forceinline__ double sel4(const double (&x)[4], int t) {
-  return t == 0 ? x[0] : t == 1 ? x[1] : t == 2 ? x[2] : x[3];
-}
-
-// The symmetric Schur rotation of the 2 x 2 block (app, apq; apq, aqq):
-// c, s with J = [[c, s], [-s, c]] and J^T A J diagonal (as the 2 x 2 leaves).
-__device__ __forceinline__ void schur2(double app, double aqq, double apq, double& c, double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (apq != 0.0) {
-    const double th = (aqq - app) / (2.0 * apq);
-    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-    c = 1.0 / sqrt(fma(t, t, 1.0));
-    s = t * c;
-  }
-}
-
-// Columns p, q of a row rotated: (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q).
-template <int P, int Q>
-__device__ __forceinline__ void rot_cols(double (&x)[4], double c, double s) {
-  const double xp = x[P], xq = x[Q];
-  x[P] = fma(c, xp, -s * xq);
-  x[Q] = fma(s, xp, c * xq);
-}
-
-// One round: pairs (P0, Q0) and (P1, Q1); PART is the DPP pattern of the
-// partner in one's own pair, OTHER that of a lane of the other pair.
-template <int P0, int Q0, int P1, int Q1, int PART, int OTHER>
-__device__ __forceinline__ void jacobi4_round(double (&A)[4], double (&V)[4], int t) {
-  const bool first = t == P0 || t == Q0;
-  const int p = first ? P0 : P1, q = first ? Q0 : Q1;
-  const bool isp = t == p;
-  // the pair's entries: a_pp and a_qq from their lanes, a_pq from row p, so
-  // that both lanes of the pair compute the same rotation
-  const double d = sel4(A, t);
-  const double dp = dpp_lane<PART>(d);
-  const double o = sel4(A, q);                 // row p: a_pq (row q: unused)
-  const double op = dpp_lane<PART>(o);
-  double c, s;
-  schur2(isp ? d : dp, isp ? dp : d, isp ? o : op, c, s);
-  const double co = dpp_lane<OTHER>(c), so = dpp_lane<OTHER>(s);
-  const double c0 = first ? c : co, s0 = first ? s : so;
-  const double c1 = first ? co : c, s1 = first ? so : s;
-  // A <- A J, V <- V J
-  rot_cols<P0, Q0>(A, c0, s0);
-  rot_cols<P1, Q1>(A, c1, s1);
-  rot_cols<P0, Q0>(V, c0, s0);
-  rot_cols<P1, Q1>(V, c1, s1);
-  // A <- J^T A: row p <- c row_p - s row_q, row q <- s row_p + c row_q
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double other = dpp_lane<PART>(A[j]);
-    A[j] = isp ? fma(c, A[j], -s * other) : fma(s, other, c * A[j]);
-  }
-}
-
-// Sum over the quad.
-__device__ __forceinline__ double quad_sum(double x) {
-  x += dpp_lane<0xB1>(x);
-  return x + dpp_lane<0x4E>(x);
-}
-
-// x[t ^ M] of lane t ^ M, for each lane t (the quad's values of register t
-// transposed through lane pairs t, t ^ M).
-template <int M>
-__device__ __forceinline__ double quad_xchg(const double (&x)[4], int t) {
-  constexpr int CTRL = M == 1 ? 0xB1 : M == 2 ? 0x4E : 0x1B;
-  return dpp_lane<CTRL>(sel4(x, t ^ M));
-}
-
-// The leaf's eigendecomposition: lam = this lane's eigenvalue, Vc = column t
-// of V (V[0..3][t]: the eigenvector of lam), Vr = row t of V.  Sweeps until
-// every leaf of the wavefront is diagonal to 1e-15 of its norm (at most 8;
-// a 4 x 4 symmetric matrix takes 3 or 4 in FP64).
-__device__ __forceinline__ void jacobi4(double (&A)[4], double& lam, double (&Vc)[4],
-                                        double (&Vr)[4], int t) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) Vr[j] = j == t ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 8; ++sweep) {
-    double off = 0.0, fro = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double a2 = A[j] * A[j];
-      fro += a2;
-      off += j == t ? 0.0 : a2;
-    }
-    off = quad_sum(off);
-    fro = quad_sum(fro);
-    if (__ballot(off > 1e-30 * fro) == 0) break;         // wave-uniform
-    jacobi4_round<0, 1, 2, 3, 0xB1, 0x4E>(A, Vr, t);
-    jacobi4_round<0, 2, 1, 3, 0x4E, 0xB1>(A, Vr, t);
-    jacobi4_round<0, 3, 1, 2, 0x1B, 0xB1>(A, Vr, t);
-  }
-  lam = sel4(A, t);
-  // column t of V: V[s][t] is lane s's entry t
-#pragma unroll
-  for (int j = 0; j < 4; ++j) Vc[j] = 0.0;
-  const double own = sel4(Vr, t);
-  const double x1 = quad_xchg<1>(Vr, t), x2 = quad_xchg<2>(Vr, t), x3 = quad_xchg<3>(Vr, t);
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int m = s ^ t;
-    Vc[s] = m == 0 ? own : m == 1 ? x1 : m == 2 ? x2 : x3;
-  }
-}
-
 // The transform of one matrix: T given by (dj, ej) on lane jj, R = this
 // lane's column of X H on entry; Y = this lane's column of Y Q_T^T and mi the
 // nine mean increments on exit.  Returns false if a secular root ran out of
@@ -674,18 +559,10 @@ __device__ __forceinline__ bool xf_tridiagonal(double (&R)[kXfUp], double dj, do
                                                XfLds<KP>& sh, int seg, int jj, double deps,
                                                double sqrt_km1, double (&Y)[kXfDown],
                                                double (&mi)[kXfDown]) {
-  // 4 x 4 leaves: T torn at every fourth coupling (Cuppen: the torn
-  // coupling comes off both diagonal entries it joins), each leaf
-  // diagonalized by Jacobi
-  const int t = jj & 3, a4 = jj & ~3;
-  const double eabove = __shfl(ej, a4 > 0 ? a4 - 1 : 0, KP);
-  const double eleft = dpp_lane<0x90>(ej);       // quad_perm [0,0,1,2]: lane t - 1's coupling
-  double dd = dj;
-  if (t == 0 && a4 > 0) dd -= eabove;
-  if (t == 3) dd -= ej;
+  // 4 x 4 leaves diagonalized by Jacobi (k_dc.h)
+  const int t = jj & 3;
   double A[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) A[j] = j == t ? dd : (j == t + 1 ? ej : (j == t - 1 ? eleft : 0.0));
+  leaf4<KP>(dj, ej, jj, A);
   double lam, Vc[4], Vr[4];
   jacobi4(A, lam, Vc, Vr, t);
   // R <- R V: entry t of each vector is sum_s R_s V[s][t]
