@@ -5,10 +5,10 @@
 //
 // Method (Cuppen 1981; Dongarra & Sorensen 1987; stable eigenvectors from
 // Gu & Eisenstat 1995):
-//   * T is torn at every other coupling (a torn coupling e_i comes off the
-//     two diagonal entries next to it), leaving 2 x 2 leaves that one Jacobi
-//     rotation each diagonalizes;
-//   * levels S = 4, 8, .., KP merge two children of size S/2 at the split
+//   * T is torn at every fourth coupling (a torn coupling e_i comes off the
+//     two diagonal entries next to it), leaving 4 x 4 leaves that cyclic
+//     Jacobi diagonalizes on a quad of lanes (jacobi4);
+//   * levels S = 8, 16, .., KP merge two children of size S/2 at the split
 //     m = a + S/2:  T_block = diag(Q1 D1 Q1^T, Q2 D2 Q2^T) + beta u u^T with
 //     beta = e_{m-1}, u = e_{m-1} + e_m, so the block's eigenproblem is the
 //     rank-one update D + beta z z^T of the children's eigenvalues, with
