@@ -440,6 +440,8 @@ def main():
     ap.add_argument("--batching-precision", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision form of the mixed batch (its recipe names the FP32 path)")
     ap.add_argument("--batching-reps", type=int, default=2)
+    ap.add_argument("--twin-cycles", type=int, default=24,
+                    help="cycles of the twin experiment on the 256 x 256, k = 32 workload (0: skip)")
     ap.add_argument("--batching-small-problems", type=int, default=256,
                     help="problems of the small-lattice batch (64 x 64 only; 0: skip)")
     ap.add_argument("--batching-tune", action="store_true")
@@ -612,6 +614,19 @@ def main():
                                              tuple(int(g) for g in args.batching_grids.split(",")),
                                              args.batching_precision, args.batching_reps,
                                              args.batching_tune)
+    if args.twin_cycles > 0:
+        # the cycled twin experiment on the 256 x 256, k = 32 workload: a nature
+        # run of the forced BGK model, its (u, v) observed every cycle
+        from paper_2308_03310_amd import twin
+        print(f"twin experiment, {args.twin_cycles} cycles", file=sys.stderr, flush=True)
+        tw = twin.run_twin(twin.TwinConfig(synth.WORKLOADS["grid256_k32"], n_cycles=args.twin_cycles,
+                                           n_steps=50), dev)
+        r3 = lambda xs: [float(f"{x:.3g}") for x in xs]
+        out["twin"] = dict(tw["summary"], forecast_rmse=r3(tw["forecast_rmse"]),
+                           analysis_rmse=r3(tw["analysis_rmse"]), free_rmse=r3(tw["free_rmse"]),
+                           spread=r3(tw["spread"]),
+                           all_status_ok=all(s_ == L.LETKF_OK for s_ in tw["status"]))
+        torch.cuda.empty_cache()
     if args.batching_small_problems > 0:
         # the same recipe restricted to 64 x 64 lattices: problems too small to
         # fill the device alone, where one call each leaves it idle between

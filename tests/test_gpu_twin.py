@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 def test_twin_experiment_reduces_error(device):
     wl = synth.Workload("twin64_k16", 64, 64, 16, 2, 0.005, 4.0, 1.1, 7)
-    cfg = twin.TwinConfig(wl, n_cycles=10, n_steps=20)
+    cfg = twin.TwinConfig(wl, n_cycles=24, n_steps=20)
     print(f"twin: {wl.nx}x{wl.ny} k={wl.k}, {cfg.n_cycles} cycles x {cfg.n_steps} steps", flush=True)
     out = twin.run_twin(cfg, device)
     sys.stdout.flush()
