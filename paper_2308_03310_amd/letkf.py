@@ -190,7 +190,10 @@ def make_io(problem: int, xb, xa, obs=None, obs_on_host: bool = False) -> letkf_
     """obs: dict or tuple of tensors (ix, iy, kind int32; val, var float64) on
     the device, or on the host for a plan made with LETKF_FLAG_OBS_ON_HOST
     (obs_on_host=True).  The element counts are kept with the descriptor and
-    checked against the plan's problem when the call is made."""
+    checked against the plan's problem when the call is made, and so are
+    references to the tensors: they live at least as long as the descriptor
+    (the calls are asynchronous, so keep it, or the tensors, until the
+    stream has run them)."""
     import torch
     if obs is None:
         n, p, counts = 0, (0, 0, 0, 0, 0), ()
@@ -206,6 +209,7 @@ def make_io(problem: int, xb, xa, obs=None, obs_on_host: bool = False) -> letkf_
     io = letkf_io(int(problem), n, _ptr(xb, torch.float64), _ptr(xa, torch.float64), *p)
     io._numel = (int(xb.numel()), int(xa.numel())) + counts
     io._obs_on_host = bool(obs_on_host) and obs is not None
+    io._keep = (xb, xa, obs)
     return io
 
 
