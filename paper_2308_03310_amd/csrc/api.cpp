@@ -145,6 +145,8 @@ struct letkf_plan_s {
   hipStream_t last_stream = nullptr;
   int form = LETKF_FORM_AUTO;       // kernel form of the Gram -> update steps (tunable)
   int* queue = nullptr;             // device [kQueueSlots]: persistent-launch work counters
+  const double** xio = nullptr;     // device [2 nprob]: {xb, xa} of the current call, read by
+                                    // the fused form (which works on them in place of xt)
   // Phase timing: a ring of event sets, one set per timed call.
   static constexpr int kSlots = 256;
   bool timing = false;
@@ -443,19 +445,36 @@ int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int 
     const ObsArgs oa = obs_args(w, io[i], status);
     return launch_bin(oa, s) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
   };
+  // the fused form works on the caller's member-major arrays: no transposes,
+  // the call's pointers go to the plan's table instead
+  auto fused_io = [&](int i) { return fused_form(pl, pl->probs[io[i].problem].kp); };
+  PtrBatch ptrs{};
+  auto flush_ptrs = [&]() -> int {
+    const hipError_t e = launch_store_ptrs(pl->xio, ptrs, s);
+    ptrs.n = 0;
+    return e == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+  };
   auto prep_transpose = [&](int i) -> int {
     const ProblemWs& w = pl->probs[io[i].problem];
+    if (fused_io(i)) {
+      ptrs.slot[ptrs.n] = io[i].problem;
+      ptrs.xb[ptrs.n] = src[i];
+      ptrs.xa[ptrs.n] = io[i].xa;
+      return ++ptrs.n == kPtrBatch ? flush_ptrs() : LETKF_OK;
+    }
     return launch_transpose_in(src[i], w.xt, w.p.k, w.npts, w.abort_flag, s) == hipSuccess
                ? LETKF_OK
                : LETKF_EDEVICE;
   };
   auto prep_obs = [&](int i) -> int {
     const ProblemWs& w = pl->probs[io[i].problem];
-    const ObsArgs oa = obs_args(w, io[i], status);
+    ObsArgs oa = obs_args(w, io[i], status);
+    if (fused_io(i)) oa.xm = src[i];
     return launch_obs_operator(oa, s) == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
   };
   auto untranspose = [&](int i) -> int {
     const ProblemWs& w = pl->probs[io[i].problem];
+    if (fused_io(i)) return LETKF_OK;
     return launch_transpose_out(w.xt, io[i].xa, w.p.k, w.npts, w.abort_flag, s) == hipSuccess
                ? LETKF_OK
                : LETKF_EDEVICE;
@@ -469,6 +488,7 @@ int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int 
     for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_bin(i);
     mk.at(1, s);
     for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_transpose(i);
+    if (rc == LETKF_OK) rc = flush_ptrs();
     mk.at(2, s);
     for (int i = 0; i < n_io && rc == LETKF_OK; ++i) rc = prep_obs(i);
     mk.at(3, s);
@@ -489,6 +509,7 @@ int enqueue(letkf_plan_s* pl, const letkf_io* io, const double* const* src, int 
     rc = prep_bin(i);
     mk.at(1, s);
     if (rc == LETKF_OK) rc = prep_transpose(i);
+    if (rc == LETKF_OK) rc = flush_ptrs();
     mk.at(2, s);
     if (rc == LETKF_OK) rc = prep_obs(i);
     mk.at(3, s);
@@ -527,6 +548,7 @@ bool upload_descriptors(letkf_plan_s* pl) {
   for (int i = 0; i < n_probs; ++i) {
     g_host[i] = gram_desc(pl->probs[i]);
     e_host[i] = evd_desc(pl->probs[i], pl->stat + 1);
+    e_host[i].xio = fused_form(pl, pl->probs[i].kp) ? pl->xio + 2 * i : nullptr;
     pre_host[2 * i] = 0;
     pre_host[2 * i + 1] = pl->probs[i].npts;
   }
@@ -888,7 +910,8 @@ int letkf_plan(const letkf_problem* probs, int32_t n_probs, const letkf_options*
   ok = ok && pl->alloc(&pl->slab_C, (size_t)c_doubles) && pl->alloc(&pl->slab_b, (size_t)b_doubles);
   // descriptors: one per problem, and one table per class
   ok = ok && pl->alloc(&pl->g_one, n_probs) && pl->alloc(&pl->e_one, n_probs) &&
-       pl->alloc(&pl->prefix_one, 2 * (size_t)n_probs) && pl->alloc(&pl->queue, kQueueSlots);
+       pl->alloc(&pl->prefix_one, 2 * (size_t)n_probs) && pl->alloc(&pl->queue, kQueueSlots) &&
+       pl->alloc(&pl->xio, 2 * (size_t)n_probs);
   for (auto& c : pl->classes) {
     const size_t n = c.members.size();
     ok = ok && pl->alloc(&c.g, n) && pl->alloc(&c.e, n) && pl->alloc(&c.prefix, n + 1);

@@ -72,9 +72,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int pl = p0 + sg;
     bool valid;
     const EvdArgs e = evd_args_of(bm, pl, valid);
-    const int pv = valid ? pl : 0;
-    xf_body<KP, true>(e, valid, sh.gram.c[sg], slot_c + sg * NB * 256, slot_b + sg * KP,
-                      e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh.xf, sg, jl);
+    const size_t pt = (size_t)e.pt0 + (valid ? pl : 0);
+    XRows xr;
+    if (e.xio) {             // the caller's member-major arrays, no point-major copy
+      xr.in = e.xio[0] + pt;
+      xr.out = const_cast<double*>(e.xio[1]) + pt;
+      xr.sc = (size_t)e.npts;
+      xr.sj = (size_t)9 * e.npts;
+    } else {
+      xr.in = xr.out = e.xt + pt * 9 * e.k;
+      xr.sc = (size_t)e.k;
+      xr.sj = 1;
+    }
+    xf_body<KP, true>(e, valid, sh.gram.c[sg], slot_c + sg * NB * 256, slot_b + sg * KP, xr, sh.xf,
+                      sg, jl);
     // the eigensolve's last reads of the slot and of LDS before the next
     // item's Gram writes them
     __threadfence_block();

@@ -147,10 +147,12 @@ __global__ __launch_bounds__(256) void k_obs_operator(ObsArgs a) {
   const int pt = y * a.nx + x;
   double val = 0.0;
   if (m < a.k) {
-    const double* f = a.xt + (size_t)pt * 9 * a.k + m;
+    // point-major [pt][9][k], or member-major [k][9][npts] when xm is set
+    const double* f = a.xm ? a.xm + (size_t)m * 9 * a.npts + pt : a.xt + (size_t)pt * 9 * a.k + m;
+    const size_t si = a.xm ? (size_t)a.npts : (size_t)a.k;
     double fi[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fi[i] = f[i * a.k];
+    for (int i = 0; i < 9; ++i) fi[i] = f[i * si];
     double rho = 0.0, ju = 0.0, jv = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -177,7 +179,21 @@ __global__ __launch_bounds__(256) void k_obs_operator(ObsArgs a) {
   }
 }
 
+__global__ void k_store_ptrs(const double** table, PtrBatch b) {
+  const int i = threadIdx.x;
+  if (i < b.n) {
+    table[2 * b.slot[i]] = b.xb[i];
+    table[2 * b.slot[i] + 1] = b.xa[i];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
+hipError_t launch_store_ptrs(const double** table, const PtrBatch& b, hipStream_t s) {
+  if (b.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_store_ptrs, dim3(1), dim3(kPtrBatch), 0, s, table, b);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);

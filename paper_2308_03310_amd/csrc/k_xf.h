@@ -599,17 +599,25 @@ __device__ __forceinline__ bool xf_tridiagonal(double (&R)[kXfUp], double dj, do
 
 // Eigensolve, transform and in-place update of the point-major ensemble for
 // 64 / KP points per wavefront (mode 0 of EvdArgs).
+// One point's ensemble values: component c of member j is in[c sc + j sj]
+// before the update and out[c sc + j sj] after it (point-major: sc = k,
+// sj = 1, in = out; member-major [k][9][npts]: sc = npts, sj = 9 npts).
+struct XRows {
+  const double* in;
+  double* out;
+  size_t sc, sj;
+};
+
 // The eigensolve, transform and update of one point on KP lanes (segment
 // seg of the wavefront): e its problem's descriptor, Cq its Gram output (the
 // upper 16 x 16 blocks of C in global memory, or with PACKED the packed upper
 // triangle in LDS, consumed before the eigensolve uses its LDS), rv global
 // scratch for the Householder vectors (k (k - 1) / 2 doubles, used when the
-// registers cannot keep them), bp its b, xp its ensemble row ([9][k],
-// updated in place).  valid false: the segment computes on padding and
-// writes nothing.
+// registers cannot keep them), bp its b, xr its ensemble values.  valid
+// false: the segment computes on padding and writes nothing.
 template <int KP, bool PACKED = false>
 __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const double* Cq, double* rv,
-                                        const double* bp, double* xp, XfLds<KP>& sh, int seg,
+                                        const double* bp, const XRows& xr, XfLds<KP>& sh, int seg,
                                         int jj) {
   constexpr int NP = KP / 16;
   const int k = e.k;
@@ -631,13 +639,14 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
   {
     // row c < 9: component c of the point's members; row 9: b; one load per
     // entry, clamped to the row (entries past k and rows past 9 are zero)
-    const double* src = c < 9 ? xp + c * k : bp;
+    const double* src = c < 9 ? xr.in + c * xr.sc : bp;
+    const size_t sj = c < 9 ? xr.sj : 1;
     const int jmax = c < 9 ? k - 1 : KP - 1;
     const bool row_ok = valid && c < kXfRows;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int j = q + NP * u;
-      const double v = ldg(src, j < jmax ? j : jmax);
+      const double v = ldg(src, (size_t)(j < jmax ? j : jmax) * sj);
       x[u] = (row_ok && j < k) ? v : 0.0;
     }
   }
@@ -698,7 +707,7 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
       if (j < k) {
         const double xa = xbar + (mic + x[u]);
         finite = finite && __builtin_isfinite(xa);
-        xp[c * k + j] = xa;
+        xr.out[c * xr.sc + j * xr.sj] = xa;
       }
     }
   }
@@ -717,8 +726,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int pv = valid ? pl : 0;
   // the reflectors' global copy goes to the point's consumed Gram output
   double* cp = gram_c(bm, pv, KP);
-  xf_body<KP>(e, valid, cp, cp, gram_b(bm, pv, KP), e.xt + (size_t)(e.pt0 + pv) * 9 * e.k, sh,
-              seg, jj);
+  double* xp = e.xt + (size_t)(e.pt0 + pv) * 9 * e.k;
+  xf_body<KP>(e, valid, cp, cp, gram_b(bm, pv, KP), XRows{xp, xp, (size_t)e.k, 1}, sh, seg, jj);
 }
 
 template <int KP>

@@ -36,6 +36,8 @@ struct ObsArgs {
   double* d;        // [n_obs] yo - ybar
   double* rinv;     // [n_obs] 1/sigma^2 (0 for an ignored observation)
   const double* xt; // point-major ensemble [npts][9][k]
+  const double* xm; // or, when not null, the member-major ensemble [k][9][npts] read
+                    // directly (the fused form, which needs no point-major copy)
   int* abort_flag;
   int* status;
 };
@@ -76,6 +78,9 @@ struct EvdArgs {
                       // scratch for the Householder reflectors once staged
   const double* b;    // [npt][KP]
   double* xt;         // point-major ensemble [npts][9][k], updated in place
+  const double* const* xio;  // fused form: {xb, xa} of the current call, member-major
+                             // [k][9][npts] (the plan's pointer table, set per call); null:
+                             // the point-major xt
   const double* A;    // mode 1: [npt][k][k]
   double* lam;        // mode 1: [npt][k]
   double* vec;        // mode 1: [npt][k][k]
@@ -209,6 +214,16 @@ __device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool&
 
 // --- launchers (return hipError_t of the launch) ---
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
+// Up to kPtrBatch (slot, xb, xa) entries of a plan's pointer table, written
+// by a kernel (so that a captured call replays them).
+constexpr int kPtrBatch = 16;
+struct PtrBatch {
+  const double* xb[kPtrBatch];
+  double* xa[kPtrBatch];
+  int slot[kPtrBatch];
+  int n;
+};
+hipError_t launch_store_ptrs(const double** table, const PtrBatch& b, hipStream_t s);
 hipError_t launch_clear_bits(int* p, int bits, hipStream_t s);
 hipError_t launch_bin(const ObsArgs& a, hipStream_t s);
 hipError_t launch_transpose_in(const double* xb, double* xt, int k, int npts, const int* abort_flag,

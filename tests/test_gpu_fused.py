@@ -85,6 +85,29 @@ def test_fused_equals_grid_512_k64(device):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("k", [40, 64])
+def test_fused_in_place_equals_out_of_place(device, k):
+    """The fused form reads and writes the caller's member-major arrays
+    directly: in place (xa = xb) it must give what it gives out of place."""
+    import torch
+    wl = synth.Workload("ragged", 40, 27, k, 3, 0.01, 3.3, 1.15, 70 + k,
+                        kinds=(synth.OBS_RHO, synth.OBS_U, synth.OBS_V))
+    p = synth.make_problem(wl)
+    say(f"ragged 40x27 k={k}: fused in place vs out of place")
+    ref, st = _run(p, L.LETKF_FORM_FUSED)
+    assert st == L.LETKF_OK
+    plan = L.letkf_plan([L.make_problem(wl.nx, wl.ny, wl.k, len(p.obs_ix), wl.L, wl.infl)])
+    try:
+        L.letkf_set_tuning(plan, 8, L.LETKF_FORM_FUSED)
+        x = torch.from_numpy(p.xb).cuda()
+        obs = _obs(p, torch)
+        L.letkf_analyze(plan, [L.make_io(0, x, x, obs)])
+        assert L.letkf_status(plan, sync=True) == L.LETKF_OK
+        assert np.array_equal(x.cpu().numpy(), ref)
+    finally:
+        L.letkf_plan_destroy(plan)
+
+
 def test_fused_invalid_observation_leaves_output(device):
     import torch
     p = synth.make_problem(synth.WORKLOADS["cpu32_k16"])
