@@ -227,9 +227,10 @@ int letkf_advance(letkf_plan_t plan, const letkf_cycle_io* io, int32_t n_io, voi
 #define LETKF_FORM_PERSISTENT 1  /* the same, the Gram launches as persistent work queues */
 #define LETKF_FORM_FUSED      2  /* one persistent launch per width class doing the Gram,
                                     eigensolve, transform and update of every point of the
-                                    call's problems, C kept in a per-wavefront slot in L2;
-                                    problems ordered by estimated cost, dearest first
-                                    (plans with LETKF_FLAG_NSQRT run it as GRID) */
+                                    call's problems on the caller's member-major arrays (no
+                                    point-major copy, C kept in LDS); problems ordered by
+                                    estimated cost, dearest first (plans with
+                                    LETKF_FLAG_NSQRT run it as GRID) */
 #define LETKF_FORM_AUTO       3  /* FUSED for the problems with 33 <= k <= 64, GRID for the
                                     narrower ones (where the Gram's own occupancy matters
                                     more than C's round trip through HBM) */
