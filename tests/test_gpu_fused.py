@@ -11,8 +11,10 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import letkf_oracle as orc
 from paper_2308_03310_amd import synth
 from paper_2308_03310_amd import letkf as L
+from _parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -106,6 +108,38 @@ def test_fused_in_place_equals_out_of_place(device, k):
         assert np.array_equal(x.cpu().numpy(), ref)
     finally:
         L.letkf_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (5, 1), (17, 2)])
+def test_fused_tiny_lattices_match_oracle(device, shape):
+    """Degenerate lattices at k = 64 (the fused form's width): one point, a
+    line, fewer points than one item's wavefronts; every point sees every
+    observation of its periodic box."""
+    nx, ny = shape
+    wl = synth.Workload(f"tiny{nx}x{ny}", nx, ny, 64, 1, 0.01, 2.0, 1.1, 90 + nx + ny)
+    # random members about a random state (the Fourier-mode truth of the
+    # recipe vanishes on lattices this small); (u, v) observed at every point
+    rng = np.random.default_rng(90 + nx + ny)
+    u0, v0 = rng.uniform(-0.05, 0.05, (2, ny, nx))
+    rho = 1.0 + 1e-3 * rng.standard_normal((64, ny, nx))
+    xb = synth.equilibrium(rho, u0 + 0.01 * rng.standard_normal((64, ny, nx)),
+                           v0 + 0.01 * rng.standard_normal((64, ny, nx)))
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    n = nx * ny
+    obs_ix = np.repeat(ix.ravel(), 2).astype(np.int32)
+    obs_iy = np.repeat(iy.ravel(), 2).astype(np.int32)
+    obs_kind = np.tile(np.array([synth.OBS_U, synth.OBS_V], dtype=np.int32), n)
+    truth = np.stack([u0.ravel(), v0.ravel()], axis=1).ravel()
+    obs_val = truth + 0.01 * rng.standard_normal(2 * n)
+    obs_var = np.full(2 * n, 1e-4)
+    p = synth.Problem(wl, np.ascontiguousarray(xb), obs_ix, obs_iy, obs_kind, obs_val, obs_var,
+                      u0, v0)
+    say(f"tiny lattice {nx}x{ny}, k=64, {len(p.obs_ix)} observations, fused")
+    got, st = _run(p, L.LETKF_FORM_FUSED)
+    assert st == L.LETKF_OK
+    ref = orc.letkf_analysis(p.xb, p.obs_ix, p.obs_iy, p.obs_kind, p.obs_val, p.obs_var, wl.L,
+                             wl.infl, orc.LOC_GAUSS)
+    assert_parity(got, ref, 1e-10, p.xb, 1e-8, f"tiny {nx}x{ny}")
 
 
 def test_fused_invalid_observation_leaves_output(device):
