@@ -65,6 +65,13 @@ __device__ __forceinline__ T ldg(const T* p, size_t i) {
   return ((const __attribute__((address_space(1))) T*)p)[i];
 }
 
+// p[i] = v as a global store (counted by the vector-memory counter only; a
+// flat store to a generic pointer also counts against the LDS one).
+template <typename T>
+__device__ __forceinline__ void stg(T* p, size_t i, T v) {
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
+
 // Make LDS writes of this wavefront visible to its other lanes (and keep the
 // compiler from moving LDS accesses across this point).
 __device__ __forceinline__ void wave_lds_sync() {

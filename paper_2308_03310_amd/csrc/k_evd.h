@@ -288,9 +288,10 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
     for (int c = i + 1; c < KP; ++c) pc[c & 3] = fma(a[c], vv[c], pc[c & 3]);
     const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
     pb[jj] = p;
-    const double K = 0.5 * tau * group_sum<KP>(p * vj);
     wave_lds_sync();
+    // p is requested before the reduction for K, which hides the read
     load_pairs<KP, c0, KP>(pp, pb);
+    const double K = 0.5 * tau * group_sum<KP>(p * vj);
     const double wj = fma(-2.0 * K, vj, p);
     a[i + 1] = fma(-wj, vv[i + 1], fma(-vj, pp[i + 1], a[i + 1]));
     if constexpr (more) {
@@ -307,19 +308,21 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
     dot_stream<KP, i + 1, c0, CH>(a, vb, vv, pc);
     const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
     pb[jj] = p;
-    const double K = 0.5 * tau * group_sum<KP>(p * vj);
     wave_lds_sync();
-    const double wj = fma(-2.0 * K, vj, p);
+    // the next column's entries and the first chunk of the rank-2 update's
+    // operands are requested before the reduction for K, which hides the reads
+    constexpr int CH2 = 8;
+    constexpr int c2 = (i + 2) & ~1;
     const double v1 = vb[i + 1], p1 = pb[i + 1];
+    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(vv, vb);
+    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(pp, pb);
+    const double K = 0.5 * tau * group_sum<KP>(p * vj);
+    const double wj = fma(-2.0 * K, vj, p);
     a[i + 1] = fma(-wj, v1, fma(-vj, p1, a[i + 1]));
     if constexpr (more) {
       alpha = group_read_c<KP, i + 2>(a[i + 1]);
       sig = group_sum<KP>(jj > i + 2 ? a[i + 1] * a[i + 1] : 0.0);
     }
-    constexpr int CH2 = 8;
-    constexpr int c2 = (i + 2) & ~1;
-    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(vv, vb);
-    load_pairs<KP, c2, cmin(c2 + CH2, KP)>(pp, pb);
     rank2_stream<KP, i + 2, c2, CH2>(a, vb, pb, vv, pp, vj, wj);
   }
   // nothing of the next step may be scheduled into this one (the

@@ -67,16 +67,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     wave_lds_sync();
     // the lane's indices, redefined for every item: nothing derived from
     // them may be hoisted out of the loop (that would keep the eigensolve's
-    // address arithmetic live through the Gram)
-    const int sg = opaque(seg), jl = opaque(jj);
+    // address arithmetic live through the Gram).  With one point per
+    // wavefront (G = 1) the point and its descriptor are uniform and live in
+    // scalar registers.
+    const int sg = G == 1 ? 0 : opaque(seg), jl = opaque(jj);
     const int pl = p0 + sg;
     bool valid;
-    const EvdArgs e = evd_args_of(bm, pl, valid);
+    EvdArgs e;
+    if constexpr (G == 1)
+      e = evd_args_uniform(bm, pl, valid);
+    else
+      e = evd_args_of(bm, pl, valid);
     const size_t pt = (size_t)e.pt0 + (valid ? pl : 0);
     XRows xr;
     if (e.xio) {             // the caller's member-major arrays, no point-major copy
-      xr.in = e.xio[0] + pt;
-      xr.out = const_cast<double*>(e.xio[1]) + pt;
+      const double* xin = G == 1 ? uniform_copy(e.xio) : e.xio[0];
+      const double* xout = G == 1 ? uniform_copy(e.xio + 1) : e.xio[1];
+      xr.in = xin + pt;
+      xr.out = const_cast<double*>(xout) + pt;
       xr.sc = (size_t)e.npts;
       xr.sj = (size_t)9 * e.npts;
     } else {

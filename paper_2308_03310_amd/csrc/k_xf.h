@@ -698,16 +698,22 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
     xf_load_refl_global<KP, ILAST>(nxt, rv, k, jj, valid);
     xf_reflect_backward_global<KP, ILAST>(x, nxt, rv, k, valid, sh, seg, jj, q);
   }
-  // X^a = xbar + mean increment + (Y Q_T^T H^T), this lane's entries of its row
+  // X^a = xbar + mean increment + (Y Q_T^T H^T), this lane's entries of its
+  // row.  The entry indices are recomputed here from a laundered part index
+  // (kept from the loads instead, they would be live through the whole
+  // eigensolve), and the stores are global ones (a flat store would also hold
+  // back the next wait for LDS).
   bool finite = true;
   if (valid && c < 9) {
+    const int qs = opaque(q);
+    double* const row = xr.out + c * xr.sc;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int j = q + NP * u;
+      const int j = qs + NP * u;
       if (j < k) {
         const double xa = xbar + (mic + x[u]);
         finite = finite && __builtin_isfinite(xa);
-        xr.out[c * xr.sc + j * xr.sj] = xa;
+        stg(row, (size_t)j * xr.sj, xa);
       }
     }
   }

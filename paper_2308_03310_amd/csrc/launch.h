@@ -212,6 +212,23 @@ __device__ __forceinline__ EvdArgs evd_args_of(const BatchMap& bm, int pl, bool&
   return e;
 }
 
+// evd_args_of for a point that a whole wavefront works on (pl uniform): the
+// same descriptor, read into scalar registers, so that the eigensolve's
+// vector registers are not spent on it.
+__device__ __forceinline__ EvdArgs evd_args_uniform(const BatchMap& bm, int pl, bool& valid) {
+  valid = pl < bm.n;
+  const int gidx = bm.g0 + (valid ? pl : 0);
+  const int prob =
+      bm.prefix ? __builtin_amdgcn_readfirstlane(find_problem(bm.prefix, bm.nprob, gidx)) : 0;
+  EvdArgs e = bm.e ? uniform_copy(bm.e + prob) : bm.e_inline;
+  e.C = bm.C;
+  e.b = bm.b;
+  e.pt0 = gidx - (bm.prefix ? __builtin_amdgcn_readfirstlane(bm.prefix[prob]) : 0) -
+          (valid ? pl : 0);
+  if (e.abort_flag && __builtin_amdgcn_readfirstlane(*e.abort_flag)) valid = false;
+  return e;
+}
+
 // --- launchers (return hipError_t of the launch) ---
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
 // Up to kPtrBatch (slot, xb, xa) entries of a plan's pointer table, written
