@@ -631,9 +631,10 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
   }
   double dj, ej;
   tridiagonalize<KP, kXfStream<KP>>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
-  if constexpr (!kXfReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
 
-  // rows of X: dX (nine components, ensemble mean removed) and b, row-part layout
+  // rows of X: dX (nine components, ensemble mean removed) and b, row-part
+  // layout; requested before the reflectors' global copy is written, so that
+  // the wait for them does not include those stores
   const int q = jj >> 4, c = jj & 15;
   double x[16];
   {
@@ -650,6 +651,7 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
       x[u] = (row_ok && j < k) ? v : 0.0;
     }
   }
+  if constexpr (!kXfReflInRegisters<KP>) store_reflectors<KP>(a, rv, k, jj, valid);
   double xbar = 0.0;
   {
     double s = 0.0;
@@ -728,7 +730,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int seg = lane / KP, jj = lane % KP;
   const int pl = blockIdx.x * G + seg;
   bool valid;
-  const EvdArgs e = evd_args_of(bm, pl, valid);
+  EvdArgs e;
+  if constexpr (G == 1)      // one point per wavefront: its descriptor in scalar registers
+    e = evd_args_uniform(bm, pl, valid);
+  else
+    e = evd_args_of(bm, pl, valid);
   const int pv = valid ? pl : 0;
   // the reflectors' global copy goes to the point's consumed Gram output
   double* cp = gram_c(bm, pv, KP);
