@@ -24,6 +24,10 @@ SOURCES = ["k_fused64.hip", "k_fused32.hip", "k_fused16.hip", "k_xf64.hip", "k_x
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 MAX_SCRATCH = 256   # bytes of private memory per lane a kernel may use
+# The fused kernels build without any: a spilled register's reload waits for
+# every memory operation the wavefront has in flight, its scattered ensemble
+# stores included.
+MAX_SCRATCH_OF = {f"k_fused{k}.hip": 0 for k in (16, 32, 64)}
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions in any device code
@@ -70,9 +74,10 @@ def _check_scratch(src: str, remarks: str) -> None:
             name = m.group(1)
             continue
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
-        if m and int(m.group(1)) > MAX_SCRATCH:
+        limit = MAX_SCRATCH_OF.get(src, MAX_SCRATCH)
+        if m and int(m.group(1)) > limit:
             raise RuntimeError(f"{src}: kernel {name} spills {m.group(1)} bytes per lane "
-                               f"(limit {MAX_SCRATCH})")
+                               f"(limit {limit})")
 
 
 def build(force: bool = True, verbose: bool = False) -> str:

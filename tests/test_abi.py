@@ -155,3 +155,20 @@ def test_tuning_calls_reject_bad_arguments(lib):
     t = L.letkf_tuning(8, 0, 0.0)
     assert lib.letkf_set_tuning(None, ctypes.byref(t)) == L.LETKF_EINVAL
     assert lib.letkf_tune(None, None, 0, None, ctypes.byref(t)) == L.LETKF_EINVAL
+
+
+def test_build_scratch_limits():
+    """The build rejects a kernel that spills more than its unit allows: none
+    at all in the fused units, up to MAX_SCRATCH bytes per lane elsewhere."""
+    from paper_2308_03310_amd import build as B
+
+    def remarks(n):
+        return ("k.h:1:1: remark: Function Name: _ZN5letkf1kEv [-Rpass-analysis=kernel-resource-usage]\n"
+                f"k.h:1:1: remark:     ScratchSize [bytes/lane]: {n} [-Rpass-analysis=kernel-resource-usage]\n")
+
+    B._check_scratch("k_fused64.hip", remarks(0))
+    B._check_scratch("k_xf32.hip", remarks(B.MAX_SCRATCH))
+    with pytest.raises(RuntimeError, match="spills 8 bytes"):
+        B._check_scratch("k_fused64.hip", remarks(8))
+    with pytest.raises(RuntimeError, match="limit 256"):
+        B._check_scratch("k_xf32.hip", remarks(B.MAX_SCRATCH + 4))
