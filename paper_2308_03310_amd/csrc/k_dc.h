@@ -374,15 +374,26 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
   if (t == 0 && scan) {
     int prev = -1, nrot = 0;
     double dp = 0.0, wp = 0.0;
+    // position k + 1 is read before position k's stores (which touch k and
+    // the positions before it only), so the reads do not wait for them
+    double wk = L.ws[a], dk = L.ds[a];
+    int ik = L.inv[a];
 #pragma unroll 8
     for (int k = 0; k < S; ++k) {
-      const double wk = L.ws[a + k], dk = L.ds[a + k];
-      if (L.inv[a + k] >= 0) {
+      double wn = 0.0, dn = 0.0;
+      int in = -1;
+      if (k + 1 < S) {
+        wn = L.ws[a + k + 1];
+        dn = L.ds[a + k + 1];
+        in = L.inv[a + k + 1];
+      }
+      if (ik >= 0) {
         const bool rot =
             prev >= 0 && fabs(dk - dp) * fabs(wk * wp) <= tol * fma(wp, wp, wk * wk);
         if (rot) {
           const double tt = sqrt(fma(wp, wp, wk * wk));
-          const double c = wk / tt, sn = wp / tt;
+          const double it = frcp(tt);
+          const double c = wk * it, sn = wp * it;
           L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
           L.ws[a + prev] = 0.0;
           L.inv[a + prev] = -1;
@@ -400,6 +411,9 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
         }
         prev = k;
       }
+      wk = wn;
+      dk = dn;
+      ik = in;
     }
     L.rot[a + S - 1] = nrot;
   }
