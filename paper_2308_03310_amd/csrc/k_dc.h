@@ -348,72 +348,70 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
   const double tol = 8.0 * deps * fmax(group_max<S>(fabs(D)), rho);
   wave_lds_sync();
   // deflation: negligible weights (lane-parallel), then pairs of close poles
-  // (a sequential scan by one lane over the sorted order).  A pair (p, k) of
-  // neighbouring surviving poles is rotated when |(d_k - d_p) c s| <= tol
+  // (sequential, by one lane per block, over the sorted order).  A pair (p, k)
+  // of neighbouring surviving poles is rotated when |(d_k - d_p) c s| <= tol
   // for the rotation (c, s) = (w_k, w_p) / |(w_p, w_k)| that zeroes w_p,
-  // i.e. |d_k - d_p| |w_k w_p| <= tol (w_p^2 + w_k^2).  The scan runs only in
-  // blocks where some pair passes that test with the unrotated values: a
-  // rotation changes only the pair it acts on, so without such a pair the
-  // scan would find none.
+  // i.e. |d_k - d_p| |w_k w_p| <= tol (w_p^2 + w_k^2).  Every pair is first
+  // tested with the unrotated values, lane-parallel (the candidates); a
+  // rotation changes only the pair it acts on (p is deflated, k takes the
+  // rotated values), so only the pair after a rotation can change its
+  // answer: the scan goes from candidate to candidate and follows each
+  // chain of rotations while the test of the next pair passes.  The
+  // decisions, their order and the arithmetic are those of a scan over
+  // every position.
   const uint64_t bmask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
   const double wt = L.ws[a + t], dtt = L.ds[a + t];
   const bool small = !(fabs(rho * wt) > tol);
   L.inv[a + t] = small ? -1 : 0;
   if (small) L.ws[a + t] = 0.0;
   const bool live = !trivial && !small;
-  const uint64_t below = (__ballot(live) >> sh0) & bmask & ((1ull << t) - 1ull);
+  const uint64_t lmask = (__ballot(live) >> sh0) & bmask;
+  const uint64_t below = lmask & ((1ull << t) - 1ull);
   bool cand = false;
   if (live && below != 0) {
     const int pp = 63 - __clzll(below);
     const double wp = L.ws[a + pp], dp = L.ds[a + pp];
     cand = fabs(dtt - dp) * fabs(wt * wp) <= tol * fma(wp, wp, wt * wt);
   }
-  const bool scan = ((__ballot(cand) >> sh0) & bmask) != 0;
+  const uint64_t cmask = (__ballot(cand) >> sh0) & bmask;
   if (t == 0) L.rot[a + S - 1] = 0;
   wave_lds_sync();
-  if (t == 0 && scan) {
-    int prev = -1, nrot = 0;
-    double dp = 0.0, wp = 0.0;
-    // position k + 1 is read before position k's stores (which touch k and
-    // the positions before it only), so the reads do not wait for them
-    double wk = L.ws[a], dk = L.ds[a];
-    int ik = L.inv[a];
-#pragma unroll 8
-    for (int k = 0; k < S; ++k) {
-      double wn = 0.0, dn = 0.0;
-      int in = -1;
-      if (k + 1 < S) {
-        wn = L.ws[a + k + 1];
-        dn = L.ds[a + k + 1];
-        in = L.inv[a + k + 1];
-      }
-      if (ik >= 0) {
-        const bool rot =
-            prev >= 0 && fabs(dk - dp) * fabs(wk * wp) <= tol * fma(wp, wp, wk * wk);
-        if (rot) {
-          const double tt = sqrt(fma(wp, wp, wk * wk));
-          const double it = frcp(tt);
-          const double c = wk * it, sn = wp * it;
-          L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
-          L.ws[a + prev] = 0.0;
-          L.inv[a + prev] = -1;
-          L.rot[a + nrot] = prev | (k << 8);
-          L.rc[a + nrot] = c;
-          L.rs[a + nrot] = sn;
-          ++nrot;
-          dp = fma(sn * sn, dp, c * c * dk);
-          wp = tt;
-          L.ds[a + k] = dp;
-          L.ws[a + k] = wp;
-        } else {
-          dp = dk;
-          wp = wk;
-        }
+  if (t == 0 && cmask != 0) {
+    uint64_t cm = cmask, lm = lmask;
+    int nrot = 0;
+    while (cm != 0) {
+      int k = __builtin_ctzll(cm);                          // a candidate and
+      int prev = 63 - __clzll(lm & ((1ull << k) - 1ull));   // its surviving left neighbour
+      double dp = L.ds[a + prev], wp = L.ws[a + prev];
+      bool end = false;
+      for (;;) {
+        const double wk = L.ws[a + k], dk = L.ds[a + k];
+        if (!(fabs(dk - dp) * fabs(wk * wp) <= tol * fma(wp, wp, wk * wk))) break;
+        const double tt = sqrt(fma(wp, wp, wk * wk));
+        const double it = frcp(tt);
+        const double c = wk * it, sn = wp * it;
+        L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
+        L.ws[a + prev] = 0.0;
+        L.inv[a + prev] = -1;
+        L.rot[a + nrot] = prev | (k << 8);
+        L.rc[a + nrot] = c;
+        L.rs[a + nrot] = sn;
+        ++nrot;
+        dp = fma(sn * sn, dp, c * c * dk);
+        wp = tt;
+        L.ds[a + k] = dp;
+        L.ws[a + k] = wp;
+        lm &= ~(1ull << prev);
         prev = k;
+        const uint64_t above = k == 63 ? 0ull : lm & ~((2ull << k) - 1ull);
+        if (above == 0) {
+          end = true;
+          break;
+        }
+        k = __builtin_ctzll(above);
       }
-      wk = wn;
-      dk = dn;
-      ik = in;
+      // the candidates up to where the chain stopped have been decided
+      cm = (end || k == 63) ? 0ull : cm & ~((2ull << k) - 1ull);
     }
     L.rot[a + S - 1] = nrot;
   }
