@@ -80,6 +80,20 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(y, e, y);
 }
 
+// 1/sqrt(x) and sqrt(x) for finite x > 0 of moderate size: hardware
+// estimate of 1/sqrt(x), two Newton-Raphson steps, then sqrt(x) = x/sqrt(x)
+// with one correction.
+__device__ __forceinline__ void rsqrt_sqrt(double x, double& r, double& s) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  double q = x * y;
+  q = fma(fma(-q, q, x), 0.5 * y, q);
+  r = y;
+  s = q;
+}
+
 // 1/x to about 10 ulps (the estimate carries about 24 bits; one
 // Newton-Raphson step): for the far terms of the secular sums, whose
 // rounding the convergence test already allows for (4 eps K sum |terms|).
@@ -383,12 +397,18 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
       int k = __builtin_ctzll(cm);                          // a candidate and
       int prev = 63 - __clzll(lm & ((1ull << k) - 1ull));   // its surviving left neighbour
       double dp = L.ds[a + prev], wp = L.ws[a + prev];
+      double wk = L.ws[a + k], dk = L.ds[a + k];
       bool end = false;
       for (;;) {
-        const double wk = L.ws[a + k], dk = L.ds[a + k];
-        if (!(fabs(dk - dp) * fabs(wk * wp) <= tol * fma(wp, wp, wk * wk))) break;
-        const double tt = sqrt(fma(wp, wp, wk * wk));
-        const double it = frcp(tt);
+        // the next surviving position and its values, read before this
+        // step's stores (which touch k and the positions below it only)
+        const uint64_t above = k == 63 ? 0ull : lm & ~((2ull << k) - 1ull);
+        const int kn = above != 0 ? __builtin_ctzll(above) : k;
+        const double wn = L.ws[a + kn], dn = L.ds[a + kn];
+        const double nn = fma(wp, wp, wk * wk);
+        if (!(fabs(dk - dp) * fabs(wk * wp) <= tol * nn)) break;
+        double it, tt;
+        rsqrt_sqrt(nn, it, tt);
         const double c = wk * it, sn = wp * it;
         L.ds[a + prev] = fma(c * c, dp, sn * sn * dk);
         L.ws[a + prev] = 0.0;
@@ -403,12 +423,13 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
         L.ws[a + k] = wp;
         lm &= ~(1ull << prev);
         prev = k;
-        const uint64_t above = k == 63 ? 0ull : lm & ~((2ull << k) - 1ull);
         if (above == 0) {
           end = true;
           break;
         }
-        k = __builtin_ctzll(above);
+        k = kn;
+        wk = wn;
+        dk = dn;
       }
       // the candidates up to where the chain stopped have been decided
       cm = (end || k == 63) ? 0ull : cm & ~((2ull << k) - 1ull);
