@@ -601,8 +601,19 @@ __device__ __forceinline__ double sel4(const double (&x)[4], int t) {
 __device__ __forceinline__ void schur2(double app, double aqq, double apq, double& c, double& s) {
   c = 1.0;
   s = 0.0;
-  if (apq != 0.0) {
-    const double th = (aqq - app) / (2.0 * apq);
+  const double a2 = 2.0 * apq, diff = aqq - app;
+  if (fabs(a2) > 1e-250 && fabs(a2) < 1e250 && fabs(diff) < 1e100 * fabs(a2)) {
+    // the usual case, from refined reciprocals and reciprocal square roots
+    // (|th| < 1e100, so th^2 + 1 and |th| + sqrt(th^2 + 1) stay in range)
+    const double th = diff * frcp(a2);
+    double r1, q1;
+    rsqrt_sqrt(fma(th, th, 1.0), r1, q1);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) * frcp(fabs(th) + q1);
+    double q2;
+    rsqrt_sqrt(fma(t, t, 1.0), c, q2);
+    s = t * c;
+  } else if (apq != 0.0) {
+    const double th = diff / a2;
     const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
     c = 1.0 / sqrt(fma(t, t, 1.0));
     s = t * c;
