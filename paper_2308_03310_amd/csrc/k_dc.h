@@ -94,6 +94,22 @@ __device__ __forceinline__ void rsqrt_sqrt(double x, double& r, double& s) {
   s = q;
 }
 
+// 1/sqrt(x) for x > 0 and 1/x for finite x != 0: the refined estimates in
+// the usual range of their argument, else the IEEE forms.
+__device__ __forceinline__ double rsqrt_any(double x) {
+  if (x > 1e-280 && x < 1e280) {
+    double r, q;
+    rsqrt_sqrt(x, r, q);
+    return r;
+  }
+  return 1.0 / sqrt(x);
+}
+__device__ __forceinline__ double rcp_any(double x) {
+  const double ax = fabs(x);
+  if (ax > 1e-280 && ax < 1e280) return frcp(x);
+  return 1.0 / x;
+}
+
 // 1/x to about 10 ulps (the estimate carries about 24 bits; one
 // Newton-Raphson step): for the far terms of the secular sums, whose
 // rounding the convergence test already allows for (4 eps K sum |terms|).
@@ -182,7 +198,7 @@ __device__ __forceinline__ double secular_model_step(double f, double t1, double
 // secular_model_step).  A bracket from the signs of f safeguards every step.
 __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, double rho,
                                             double& tau_out, bool& conv) {
-  const double irho = 1.0 / rho;
+  const double irho = rcp_any(rho);
   const bool last = i == K - 1;
   const double di = dw[i].x;
   const double di1 = last ? di : dw[i + 1].x;
@@ -348,7 +364,7 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
   const double rho = fabs(beta) * nz2;
   const bool trivial = !(rho > 0.0);               // uniform per block
   mr.trivial = trivial;
-  const double w = trivial ? 0.0 : z / sqrt(nz2);
+  const double w = trivial ? 0.0 : z * rsqrt_any(nz2);
   // sort the poles (ties by index)
   int rank = 0;
 #pragma unroll 8
@@ -465,7 +481,7 @@ __device__ __forceinline__ MergeRoots merge_roots(double z, double lam, double b
   // Loewner: zhat_j^2 = (1/rho) prod_i (lambda_i - d_j) / prod_{i != j} (d_i - d_j)
   if (t < K) {
     const double dj = L.dw[2 * a + t].x;
-    double prod = 1.0 / rho;
+    double prod = rcp_any(rho);
 #pragma unroll 8
     for (int i = 0; i < S; ++i) {
       if (i < K) {
@@ -538,7 +554,7 @@ __device__ __forceinline__ void dc_merge(double (&qs)[KP], double& lam, DcLds<KP
         nrm = fma(v, v, nrm);
         Wb[(L.rw[a + u] & kRowMask) * WS + t] = v;
       }
-      cs = 1.0 / sqrt(nrm);
+      cs = rsqrt_any(nrm);
       lam_new = dorg + tau;
     }
     // deflation rotations, last first, on rows pm[p], pm[j] of this column

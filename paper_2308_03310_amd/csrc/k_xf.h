@@ -420,7 +420,7 @@ __device__ __forceinline__ void xf_merge_up(double (&R)[kXfUp], double& lam, dou
           acc[v + 1] = fma(w, x2.y, acc[v + 1]);
         }
       }
-      const double cs = 1.0 / sqrt(nrm);
+      const double cs = rsqrt_any(nrm);
 #pragma unroll
       for (int v = 0; v < kXfUp; ++v) R[v] = acc[v] * cs;
       lam_new = dorg + tau;
@@ -535,8 +535,8 @@ __device__ __forceinline__ void xf_levels(double (&R)[kXfUp], double lam, double
                                           int seg, int jj, double deps, double sqrt_km1, bool& ok,
                                           double (&Y)[kXfDown], double (&mi)[kXfDown]) {
   if constexpr (S > KP) {
-    const double y = R[9] / lam;
-    const double d2 = sqrt_km1 / sqrt(lam);
+    const double y = R[9] * rcp_any(lam);
+    const double d2 = sqrt_km1 * rsqrt_any(lam);
 #pragma unroll
     for (int c = 0; c < kXfDown; ++c) {
       mi[c] = group_sum<KP>(R[c] * y);
