@@ -268,10 +268,15 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
   double* pb = &sh.wb[0][0] + so;
   const double x = a[i];                                   // A[jj][i]
   const bool refl = sig != 0.0;                             // uniform per matrix
-  const double nrm = sqrt(fma(alpha, alpha, sig));
+  // |x| = sqrt(alpha^2 + sig) with its reciprocal (refined estimates, for
+  // column norms between 1e-154 and 1e154; a zero column takes no
+  // reflection and the values are not used); with beta = -sign(alpha) |x|,
+  // tau = 1 + |alpha| / |x| and 1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)
+  double rn, nrm;
+  rsqrt_sqrt(fma(alpha, alpha, sig), rn, nrm);
   const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-  const double tau = refl ? (beta - alpha) * frcp(beta) : 0.0;
-  const double inv = refl ? frcp(alpha - beta) : 0.0;
+  const double tau = refl ? fma(fabs(alpha), rn, 1.0) : 0.0;
+  const double inv = refl ? (alpha >= 0.0 ? 1.0 : -1.0) * frcp(fabs(alpha) + nrm) : 0.0;
   const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
   vb[jj] = vj;
   if (taus != nullptr && jj == 0) taus[i] = tau;
