@@ -259,7 +259,7 @@ __device__ __forceinline__ void rank2_stream(double (&x)[KP], const double* vsrc
 // Step i of the reduction (a compile-time index so that a[] stays in
 // registers at every size); alpha = A[i+1][i] and sig = sum_{j>i+1} A[j][i]^2
 // come in from the step before and go out for the step after.
-template <int KP, int i, bool STREAM, class Sh>
+template <int KP, int i, bool STREAM, bool UNIT, class Sh>
 __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, int jj,
                                              double& alpha, double& sig, double& ej,
                                              double* taus) {
@@ -270,17 +270,32 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
   const bool refl = sig != 0.0;                             // uniform per matrix
   // |x| = sqrt(alpha^2 + sig) with its reciprocal (refined estimates, for
   // column norms between 1e-154 and 1e154; a zero column takes no
-  // reflection and the values are not used); with beta = -sign(alpha) |x|,
-  // tau = 1 + |alpha| / |x| and 1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)
-  double rn, nrm;
-  rsqrt_sqrt(fma(alpha, alpha, sig), rn, nrm);
-  const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-  const double tau = refl ? fma(fabs(alpha), rn, 1.0) : 0.0;
-  const double inv = refl ? (alpha >= 0.0 ? 1.0 : -1.0) * frcp(fabs(alpha) + nrm) : 0.0;
-  const double vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
-  vb[jj] = vj;
-  if (taus != nullptr && jj == 0) taus[i] = tau;
+  // reflection and the values are not used), beta = -sign(alpha) |x|.
+  // UNIT: v = x / (alpha - beta), v_{i+1} = 1, tau = 1 + |alpha| / |x|
+  // (1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)).  Otherwise v is
+  // the column itself below i+1 and v_{i+1} = alpha - beta, tau = 2 / v^T v:
+  // all of v but one entry is known before the norm, so v is broadcast and
+  // A v formed (but for that entry's term) while the norm is computed.
+  double rn, nrm, tau, vj, v1 = 1.0;
+  if constexpr (UNIT) {
+    rsqrt_sqrt(fma(alpha, alpha, sig), rn, nrm);
+    tau = refl ? fma(fabs(alpha), rn, 1.0) : 0.0;
+    const double inv = refl ? (alpha >= 0.0 ? 1.0 : -1.0) * frcp(fabs(alpha) + nrm) : 0.0;
+    vj = jj == i + 1 ? 1.0 : (jj > i + 1 ? x * inv : 0.0);
+    vb[jj] = vj;
+  } else {
+    vj = jj > i + 1 ? x : 0.0;
+    vb[jj] = vj;                       // entry i+1 is 0 in LDS: its term is added apart
+  }
   wave_lds_sync();
+  if constexpr (!UNIT) {
+    rsqrt_sqrt(fma(alpha, alpha, sig), rn, nrm);
+    v1 = refl ? (alpha >= 0.0 ? 1.0 : -1.0) * (fabs(alpha) + nrm) : 0.0;   // alpha - beta
+    tau = refl ? 2.0 * frcp(fma(v1, v1, sig)) : 0.0;
+    vj = jj == i + 1 ? v1 : vj;
+  }
+  const double beta = refl ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+  if (taus != nullptr && jj == 0) taus[i] = tau;
   constexpr int c0 = (i + 1) & ~1;
   constexpr bool more = i + 1 < KP - 2;                     // a step follows
   if constexpr (!STREAM) {
@@ -288,6 +303,7 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
     // reads each (one wait per vector instead of one per few products)
     double vv[KP], pp[KP];
     load_pairs<KP, c0, KP>(vv, vb);
+    if constexpr (!UNIT) vv[i + 1] = v1;
     double pc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = i + 1; c < KP; ++c) pc[c & 3] = fma(a[c], vv[c], pc[c & 3]);
@@ -311,14 +327,17 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
     load_pairs<KP, c0, cmin(c0 + CH, KP)>(vv, vb);
     double pc[4] = {0.0, 0.0, 0.0, 0.0};
     dot_stream<KP, i + 1, c0, CH>(a, vb, vv, pc);
-    const double p = jj > i ? ((pc[0] + pc[1]) + (pc[2] + pc[3])) * tau : 0.0;
+    double dot = (pc[0] + pc[1]) + (pc[2] + pc[3]);
+    if constexpr (!UNIT) dot = fma(a[i + 1], v1, dot);       // the term of v_{i+1}
+    const double p = jj > i ? dot * tau : 0.0;
     pb[jj] = p;
     wave_lds_sync();
     // the next column's entries and the first chunk of the rank-2 update's
     // operands are requested before the reduction for K, which hides the reads
     constexpr int CH2 = 8;
     constexpr int c2 = (i + 2) & ~1;
-    const double v1 = vb[i + 1], p1 = pb[i + 1];
+    if constexpr (UNIT) v1 = vb[i + 1];
+    const double p1 = pb[i + 1];
     load_pairs<KP, c2, cmin(c2 + CH2, KP)>(vv, vb);
     load_pairs<KP, c2, cmin(c2 + CH2, KP)>(pp, pb);
     const double K = 0.5 * tau * group_sum<KP>(p * vj);
@@ -341,26 +360,28 @@ __device__ __forceinline__ void tridiag_step(double (&a)[KP], Sh& sh, int seg, i
   asm volatile("" : "+v"(ej));
 }
 
-template <int KP, bool STREAM, class Sh, int... Is>
+template <int KP, bool STREAM, bool UNIT, class Sh, int... Is>
 __device__ __forceinline__ void tridiag_steps(double (&a)[KP], Sh& sh, int seg, int jj,
                                               double& ej, double* taus,
                                               std::integer_sequence<int, Is...>) {
   double alpha = group_read_c<KP, 1>(a[0]);
   double sig = group_sum<KP>(jj > 1 ? a[0] * a[0] : 0.0);
-  (tridiag_step<KP, Is, STREAM>(a, sh, seg, jj, alpha, sig, ej, taus), ...);
+  (tridiag_step<KP, Is, STREAM, UNIT>(a, sh, seg, jj, alpha, sig, ej, taus), ...);
 }
 
 // The reduction; lane jj ends with dj = T[jj][jj] and ej = T[jj+1][jj]
-// (e_{KP-1} = 0).  The reflectors' tau values are not kept: the
-// back-transformation recovers each from its vector (tau = 2 / v^T v).
-// taus (nullable): this matrix's KP - 2 reflector tau values, written to LDS
-// by its first lane.  STREAM: the broadcast vectors come from LDS in chunks
-// (fewer registers) rather than in one burst.
-template <int KP, bool STREAM = (KP > 32), class Sh>
+// (e_{KP-1} = 0).  UNIT: the reflectors are scaled to v_{i+1} = 1 and their
+// tau values are not kept (the back-transformation recovers each from its
+// vector, tau = 2 / v^T v); otherwise they are left unscaled and taus (this
+// matrix's KP - 2 values, written to LDS by its first lane) must be given.
+// STREAM: the broadcast vectors come from LDS in chunks (fewer registers)
+// rather than in one burst.
+template <int KP, bool STREAM = (KP > 32), bool UNIT = true, class Sh>
 __device__ __forceinline__ void tridiagonalize(double (&a)[KP], Sh& sh, int seg, int jj,
                                                double& dj, double& ej, double* taus = nullptr) {
   ej = 0.0;
-  tridiag_steps<KP, STREAM>(a, sh, seg, jj, ej, taus, std::make_integer_sequence<int, KP - 2>{});
+  tridiag_steps<KP, STREAM, UNIT>(a, sh, seg, jj, ej, taus,
+                                  std::make_integer_sequence<int, KP - 2>{});
   double dg = 0.0;
 #pragma unroll
   for (int u = 0; u < KP; ++u) dg = u == jj ? a[u] : dg;

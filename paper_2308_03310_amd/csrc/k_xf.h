@@ -630,7 +630,7 @@ __device__ __forceinline__ void xf_body(const EvdArgs& e, bool valid, const doub
     xf_load_row<KP>(e, Cq, jj, valid, a);
   }
   double dj, ej;
-  tridiagonalize<KP, kXfStream<KP>>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
+  tridiagonalize<KP, kXfStream<KP>, false>(a, sh, seg, jj, dj, ej, sh.taus[seg]);
 
   // rows of X: dX (nine components, ensemble mean removed) and b, row-part
   // layout; requested before the reflectors' global copy is written, so that
