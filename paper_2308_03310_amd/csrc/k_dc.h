@@ -263,38 +263,70 @@ __device__ __forceinline__ int secular_root(const double2* dw, int K, int i, dou
   const double2* far = dw + e2 + 1;
   const int nfar = K - 2;
   conv = false;
+  // sum |terms| of the far terms, for the convergence test's rounding bound:
+  // taken at the first iterate (it changes little as the iterate converges
+  // and only scales the test)
+  double A = 0.0;
   for (int it = 0; it < kSecularMaxIts; ++it) {
-    // F, sum |terms|, F' and F''/2 of the far terms at tau, in two chains
-    double F0 = 0.0, A0 = 0.0, D0 = 0.0, E0 = 0.0;
-    double F1 = 0.0, A1 = 0.0, D1 = 0.0, E1 = 0.0;
+    // F, F' and F''/2 of the far terms at tau, in two chains
+    double F0 = 0.0, D0 = 0.0, E0 = 0.0;
+    double F1 = 0.0, D1 = 0.0, E1 = 0.0;
     int o = 0;
+    if (it == 0) {
+      double A0 = 0.0, A1 = 0.0;
 #pragma unroll 4
-    for (; o + 1 < nfar; o += 2) {
-      const double2 p = far[o], q = far[o + 1];
-      const double r0 = frcp1((p.x - dorg) - tau);
-      const double r1 = frcp1((q.x - dorg) - tau);
-      const double t0 = p.y * r0, t1 = q.y * r1;
-      const double u0 = t0 * r0, u1 = t1 * r1;
-      F0 += t0;
-      A0 += fabs(t0);
-      D0 += u0;
-      E0 = fma(u0, r0, E0);
-      F1 += t1;
-      A1 += fabs(t1);
-      D1 += u1;
-      E1 = fma(u1, r1, E1);
+      for (; o + 1 < nfar; o += 2) {
+        const double2 p = far[o], q = far[o + 1];
+        const double r0 = frcp1((p.x - dorg) - tau);
+        const double r1 = frcp1((q.x - dorg) - tau);
+        const double t0 = p.y * r0, t1 = q.y * r1;
+        const double u0 = t0 * r0, u1 = t1 * r1;
+        F0 += t0;
+        A0 += fabs(t0);
+        D0 += u0;
+        E0 = fma(u0, r0, E0);
+        F1 += t1;
+        A1 += fabs(t1);
+        D1 += u1;
+        E1 = fma(u1, r1, E1);
+      }
+      if (o < nfar) {
+        const double2 p = far[o];
+        const double r0 = frcp1((p.x - dorg) - tau);
+        const double t0 = p.y * r0;
+        const double u0 = t0 * r0;
+        F0 += t0;
+        A0 += fabs(t0);
+        D0 += u0;
+        E0 = fma(u0, r0, E0);
+      }
+      A = A0 + A1;
+    } else {
+#pragma unroll 4
+      for (; o + 1 < nfar; o += 2) {
+        const double2 p = far[o], q = far[o + 1];
+        const double r0 = frcp1((p.x - dorg) - tau);
+        const double r1 = frcp1((q.x - dorg) - tau);
+        const double t0 = p.y * r0, t1 = q.y * r1;
+        const double u0 = t0 * r0, u1 = t1 * r1;
+        F0 += t0;
+        D0 += u0;
+        E0 = fma(u0, r0, E0);
+        F1 += t1;
+        D1 += u1;
+        E1 = fma(u1, r1, E1);
+      }
+      if (o < nfar) {
+        const double2 p = far[o];
+        const double r0 = frcp1((p.x - dorg) - tau);
+        const double t0 = p.y * r0;
+        const double u0 = t0 * r0;
+        F0 += t0;
+        D0 += u0;
+        E0 = fma(u0, r0, E0);
+      }
     }
-    if (o < nfar) {
-      const double2 p = far[o];
-      const double r0 = frcp1((p.x - dorg) - tau);
-      const double t0 = p.y * r0;
-      const double u0 = t0 * r0;
-      F0 += t0;
-      A0 += fabs(t0);
-      D0 += u0;
-      E0 = fma(u0, r0, E0);
-    }
-    const double F = F0 + F1, A = A0 + A1, Fd = D0 + D1, Fh = E0 + E1;
+    const double F = F0 + F1, Fd = D0 + D1, Fh = E0 + E1;
     const double g1 = P1 - tau, g2 = P2 - tau;
     const double t1 = e1 >= 0 ? W1 * frcp(g1) : 0.0;
     const double t2 = W2 * frcp(g2);
