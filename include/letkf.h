@@ -306,10 +306,11 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
  *   vec: device, [batch][k][k], column j is the eigenvector of lam[j].
  *   status: device int32 (may be NULL); bit (1 << LETKF_ENOTCONV) is OR-ed
  *        in if a matrix did not converge.
- * The reciprocals and square roots of the reduction and the merges use
- * refined hardware estimates: entries and column norms are expected between
- * about 1e-150 and 1e150 in magnitude (or exactly zero); scale a matrix by a
- * power of two beforehand (and its eigenvalues back) if it lies outside.
+ * Each matrix is scaled by a power of two (exact) so that its largest entry
+ * lies in [0.5, 1) before the solve, and its eigenvalues are scaled back, so
+ * the result does not depend on the matrix's magnitude; entries smaller than
+ * about 2^-1022 times the largest are flushed in that scaling.  A matrix with
+ * a non-finite entry gives non-finite results.
  * Asynchronous on hip_stream.  Returns LETKF_EINVAL for bad sizes or NULL
  * pointers.
  */

@@ -17,8 +17,10 @@
 //   2. eigenpairs of T by divide and conquer (k_dc.h): T = Q_T diag(lam) Q_T^T;
 //   3. back-transformation V = H Q_T = H_0 (H_1 (.. H_{n-3} Q_T)), one column
 //      of V per lane.
-// Sizes below KP are padded with decoupled unit rows: their couplings in T are
-// exactly zero, so every merge that involves them is trivial or deflates them.
+// Sizes below KP are padded with decoupled rows (unit rows in mode 0, where
+// every eigenvalue is at least alpha; zero rows in mode 1): their couplings in
+// T are exactly zero, so every merge that involves them is trivial or deflates
+// them.
 #pragma once
 #include "common.h"
 #include "launch.h"
@@ -102,11 +104,13 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
-// Q = alpha I + C (mode 0, upper blocks mirrored) or A (mode 1) into the
-// matrix area, padded rows = unit; this lane's entry of b into bj (mode 0).
+// Q = alpha I + C (mode 0, upper blocks mirrored; padded rows unit) or A
+// (mode 1; padded rows zero, scaled by 2^-ex) into the matrix area; this
+// lane's entry of b into bj (mode 0).  ex is 0 in mode 0.
 template <int KP>
 __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, int seg, int jj,
-                                             int pl, bool valid, double& bj) {
+                                             int pl, bool valid, double& bj, int& ex) {
+  ex = 0;
   constexpr int NQ = KP / 16;
   constexpr int NB = NQ * (NQ + 1) / 2;
   constexpr int S = EvdLds<KP>::S;
@@ -145,13 +149,28 @@ __device__ __forceinline__ void stage_matrix(const EvdArgs& e, EvdLds<KP>& sh, i
       M[jj * S + jj] = 1.0;
     bj = (valid && jj < k) ? e.b[(size_t)pl * KP + jj] : 0.0;
   } else {
+    // padded rows stay zero: their eigenvalue 0 never exceeds the largest
+    // |eigenvalue| of the matrix, so it leaves the deflation tolerance of
+    // every merge (which scales with that) at the matrix's own scale
+    double amax = 0.0;
     for (int c = 0; c < KP; ++c) {
-      double val = c == jj ? 1.0 : 0.0;
+      double val = 0.0;
       if (valid && jj < k && c < k) {
         const int r0 = jj < c ? jj : c, c0 = jj < c ? c : jj;
         val = e.A[((size_t)pl * k + r0) * k + c0];
       }
+      amax = fmax(amax, fabs(val));
       M[jj * S + c] = val;
+    }
+    // An exact power-of-two scaling brings the largest entry into [0.5, 1):
+    // the hardware reciprocal and square-root estimates of the reduction and
+    // the merges then see operands of moderate size whatever the matrix's
+    // scale, and the eigenvalues are scaled back on output.  (Each lane
+    // rescales only its own row, so no barrier is needed.)
+    amax = group_max<KP>(amax);
+    if (amax > 0.0 && __builtin_isfinite(amax)) {
+      (void)frexp(amax, &ex);
+      for (int c = 0; c < KP; ++c) M[jj * S + c] = ldexp(M[jj * S + c], -ex);
     }
   }
 }
@@ -655,7 +674,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   bool valid;
   const EvdArgs e = evd_args_of(bm, pl, valid);
   double bj = 0.0;
-  stage_matrix<KP>(e, sh, seg, jj, pl, valid, bj);
+  int ex;
+  stage_matrix<KP>(e, sh, seg, jj, pl, valid, bj, ex);
   wave_lds_sync();
   // Scratch for the reflectors when they do not stay in registers through
   // the divide and conquer: this point's Gram output (mode 0, consumed by the
@@ -679,7 +699,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LETKF_EVD_WA
   wave_lds_sync();
   back_transform<KP>(q, a, rv, e.k, sh, seg, jj);
   if (e.mode != 0) {
-    write_eig<KP>(e, sh.mat[seg], seg, jj, pl, valid, lam);
+    write_eig<KP>(e, sh.mat[seg], seg, jj, pl, valid, ldexp(lam, ex));
     return;
   }
   if (e.prec == 0)

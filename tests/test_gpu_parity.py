@@ -105,7 +105,8 @@ def test_eigh_batched_random(k):
 def _hard_matrices(k, family, n, rng):
     """Batches of symmetric k x k matrices that stress a divide-and-conquer
     eigensolver: nearly equal eigenvalues, Wilkinson's close pairs, weakly
-    coupled blocks, a graded spectrum, and the LETKF form with multiplicity."""
+    coupled blocks, a graded spectrum, entries of magnitude 1e+-90 and
+    1e+-140, and the LETKF form with multiplicity."""
     def orth(m):
         q, r = np.linalg.qr(rng.standard_normal((m, m)))
         return q * np.sign(np.diag(r))
@@ -138,6 +139,9 @@ def _hard_matrices(k, family, n, rng):
         elif family == "graded":          # eigenvalues from 1e-6 to 1e6
             Q = orth(k)
             out[b] = (Q * np.logspace(-6, 6, k)) @ Q.T
+        elif family == "scaled":          # random, scaled to 1e+-90 and 1e+-140
+            B = rng.standard_normal((k, k))
+            out[b] = (B + B.T) * (1e-140, 1e-90, 1e90, 1e140)[b % 4]
         else:                             # letkf: alpha I + rank-r PSD, r < k
             r = int(rng.integers(1, k))
             Y = rng.standard_normal((r, k)) * np.sqrt(rng.uniform(0.1, 1e4, r))[:, None]
@@ -146,7 +150,7 @@ def _hard_matrices(k, family, n, rng):
     return 0.5 * (out + out.transpose(0, 2, 1))
 
 
-@pytest.mark.parametrize("family", ["clusters", "wilkinson", "glued", "graded", "letkf"])
+@pytest.mark.parametrize("family", ["clusters", "wilkinson", "glued", "graded", "scaled", "letkf"])
 @pytest.mark.parametrize("k", [16, 21, 33, 64])
 def test_eigh_batched_hard_families(k, family):
     import torch
