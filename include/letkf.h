@@ -309,8 +309,8 @@ int letkf_phase_times(letkf_plan_t plan, double* ms, int32_t* launches, int32_t 
  * Each matrix is scaled by a power of two (exact) so that its largest entry
  * lies in [0.5, 1) before the solve, and its eigenvalues are scaled back, so
  * the result does not depend on the matrix's magnitude; entries smaller than
- * about 2^-1022 times the largest are flushed in that scaling.  A matrix with
- * a non-finite entry gives non-finite results.
+ * about 2^-1022 times the largest are flushed in that scaling.  Entries must
+ * be finite (a NaN or infinite entry leaves the results undefined).
  * Asynchronous on hip_stream.  Returns LETKF_EINVAL for bad sizes or NULL
  * pointers.
  */
