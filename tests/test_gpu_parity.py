@@ -174,6 +174,44 @@ def test_eigh_batched_hard_families(k, family):
         assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
 
 
+@pytest.mark.parametrize("k", [1, 5, 16, 33, 64])
+def test_eigh_batched_power_of_two_scaling(k):
+    """Scaling the input by 2^s (exact) scales the eigenvalues by 2^s and
+    leaves the eigenvectors unchanged, bit for bit, up to magnitudes near the
+    ends of the FP64 range (each matrix is brought to a largest entry in
+    [0.5, 1) before the solve); the unscaled run matches numpy.  A zero
+    matrix and k = 1 are the degenerate cases."""
+    import torch
+    n = 16
+    rng = np.random.default_rng(500 + k)
+    B = rng.standard_normal((n, k, k))
+    A = B + B.transpose(0, 2, 1)
+    A[3] = 0.0
+
+    def run(M):
+        lam = torch.empty(n, k, dtype=torch.float64, device="cuda")
+        vec = torch.empty(n, k, k, dtype=torch.float64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        L.letkf_eigh_batched(torch.from_numpy(M).cuda(), lam, vec, st)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == 0
+        return lam.cpu().numpy(), vec.cpu().numpy()
+
+    say(f"eigh_batched k={k}: scales 2^0, 2^-900, 2^900")
+    lam0, vec0 = run(A)
+    for i in range(n):
+        nrm = max(np.linalg.norm(A[i]), 1e-300)
+        np.testing.assert_allclose(np.sort(lam0[i]), np.linalg.eigvalsh(A[i]), rtol=0,
+                                   atol=1e-13 * nrm)
+        V = vec0[i]
+        assert np.linalg.norm(V @ np.diag(lam0[i]) @ V.T - A[i]) <= 1e-13 * nrm * k
+        assert np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13 * k
+    for e in (-900, 900):
+        lam, vec = run(np.ldexp(A, e))
+        assert np.array_equal(lam, np.ldexp(lam0, e))
+        assert np.array_equal(vec, vec0)
+
+
 @pytest.mark.parametrize("k", [51, 52, 60])
 def test_eigh_batched_secular_near_pole_pairs(k):
     # Wilkinson batches at these orders give merges where a root lies within
