@@ -172,6 +172,10 @@ typedef struct letkf_io {
  * variance > 0 or +inf, finite value) set the plan status to LETKF_EINVAL and
  * skip the analysis of that problem.  In-place (xa == xb) is legal: the
  * background is fully consumed before any analysis value is written.
+ * The eigensolve of each point's ((k-1)/rho) I + C uses refined hardware
+ * reciprocal and square-root estimates: the entries of C (observation-space
+ * spread products over variances) are expected to be exactly zero or
+ * between about 1e-150 and 1e150 in magnitude.
  */
 int letkf_analyze(letkf_plan_t plan, const letkf_io* io, int32_t n_io, void* hip_stream);
 
