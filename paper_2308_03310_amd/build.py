@@ -42,6 +42,12 @@ FLAGS = [
 # (register spills); the sources also make the lane index opaque for the same
 # reason at the IR level.
 EXTRA = {f"k_fused{k}.hip": ["-mllvm", "-disable-machine-licm"] for k in (16, 32, 64)}
+# The k = 64 unit (every width from 33 to 64): LLVM's iterative scheduler
+# that keeps the occupancy (two wavefronts per SIMD) and then minimizes
+# latency.  Measured on the 1024^2, k = 64 analysis: 102.1 -> 99.5 ms (FP32
+# form), 121.2 -> 116.1 ms (FP64), bitwise the same results; the
+# instruction-level-parallelism and memory-clause strategies were no faster.
+EXTRA["k_fused64.hip"] += ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]
 
 
 def _compile(src: str, force: bool) -> str:
