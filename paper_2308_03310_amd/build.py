@@ -48,6 +48,10 @@ EXTRA = {f"k_fused{k}.hip": ["-mllvm", "-disable-machine-licm"] for k in (16, 32
 # form), 121.2 -> 116.1 ms (FP64), bitwise the same results; the
 # instruction-level-parallelism and memory-clause strategies were no faster.
 EXTRA["k_fused64.hip"] += ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]
+# The same for the split form's k = 64 eigensolve and update (1024^2, k = 64:
+# 102.0 -> 101.0 ms FP32 form, 124.0 -> 120.2 ms FP64, bitwise the same); at
+# k = 32 it made no difference and the default stays.
+EXTRA["k_xf64.hip"] = ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]
 
 
 def _compile(src: str, force: bool) -> str:
