@@ -46,7 +46,9 @@ EXTRA = {f"k_fused{k}.hip": ["-mllvm", "-disable-machine-licm"] for k in (16, 32
 # that keeps the occupancy (two wavefronts per SIMD) and then minimizes
 # latency.  Measured on the 1024^2, k = 64 analysis: 102.1 -> 99.5 ms (FP32
 # form), 121.2 -> 116.1 ms (FP64), bitwise the same results; the
-# instruction-level-parallelism and memory-clause strategies were no faster.
+# instruction-level-parallelism and memory-clause strategies, and turning off
+# either of its rescheduling stages, were no faster, and the
+# register-minimizing strategy was 11 % slower.
 EXTRA["k_fused64.hip"] += ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]
 # The same for the split form's k = 64 eigensolve and update (1024^2, k = 64:
 # 102.0 -> 101.0 ms FP32 form, 124.0 -> 120.2 ms FP64, bitwise the same); at
